@@ -1,0 +1,18 @@
+"""FP64 CPU oracle for RM synthesis -- test infrastructure only.
+
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  It shares no code with the GPU library.
+"""
+from .oracle import (  # noqa: F401
+    build,
+    lib_path,
+    plan,
+    plan_info,
+    cost_flop,
+    fdf,
+    rmsf,
+    peaks,
+    fdf_bruteforce,
+    per_los_error,
+    peak_agreement,
+)
