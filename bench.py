@@ -1,0 +1,216 @@
+#!/usr/bin/env python3
+"""Throughput of the RM-synthesis hot path on one MI355X.
+
+One step = rmsynth_execute (phase generation + split-bfloat16 MFMA
+contraction + epilogue) followed by rmsynth_peaks, over the whole synthetic
+cube, with the cube already resident in HBM.  Default workload: 1024 x 1024
+LOS, 400 channels 700-1800 MHz, phi -2000..2000 step 2 (2001 values),
+LOS-major.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3]
+                    [--precision bf16x3|fp32] [--no-cpu-baseline] [--no-fp32-compare]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+MFMA_PEAK_TFLOPS = {"bf16x3": 2516.6, "fp16x3": 2516.6, "fp32": 157.3}
+MFMA_FLOP_PER_SAMPLE = {"bf16x3": 24.0, "fp16x3": 24.0, "fp32": 8.0}
+HBM_PEAK_GBS = 8000.0
+METRIC = "LOS·chan·φ Gsamples/s + % MFMA peak, split-BF16 vs FP32 at ≤1e-5 rel err"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c3")
+    ap.add_argument("--precision", default="bf16x3", choices=["bf16x3", "fp32"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32-compare", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    return ap.parse_args()
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def time_path(rs, plan, cube, prec, Fq, Fu, pk, steps, warmup):
+    """Run warmup + timed steps; returns wall ms/step and per-kernel event ms."""
+    import torch
+    layout = cube["layout"]
+    nlos = cube["nlos"]
+
+    def step():
+        rs.rmsynth_execute(plan.handle, cube["Q"], cube["U"], nlos, layout, prec, Fq, Fu)
+        rs.rmsynth_peaks(plan.handle, Fq, Fu, nlos, pk["idx"], pk["phi_pk"], pk["amp"],
+                         pk["q_pk"], pk["u_pk"])
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+           torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for e0, e1, e2 in ev:
+        e0.record()
+        rs.rmsynth_execute(plan.handle, cube["Q"], cube["U"], nlos, layout, prec, Fq, Fu)
+        e1.record()
+        rs.rmsynth_peaks(plan.handle, Fq, Fu, nlos, pk["idx"], pk["phi_pk"], pk["amp"],
+                         pk["q_pk"], pk["u_pk"])
+        e2.record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / steps
+    ex = float(np.mean([a.elapsed_time(b) for a, b, _ in ev]))
+    pkms = float(np.mean([b.elapsed_time(c) for _, b, c in ev]))
+    return wall, ex, pkms
+
+
+def cpu_baseline_leg(cube, sub, gpu_out, seconds):
+    """Time the FP64 oracle on host cores over a bounded sample of the same
+    workload, and report the error of each GPU path on the stratified subsample."""
+    import oracle
+    import torch
+    oracle.build(force=False)
+    lam, w, phi = cube["lambda2"], cube["weights"], cube["phi"]
+    subt = torch.as_tensor(sub, device="cuda")
+
+    def rows(idx_t):
+        if cube["layout"] == 0:
+            q, u = cube["Q"][idx_t], cube["U"][idx_t]
+        else:
+            q, u = cube["Q"][:, idx_t].t(), cube["U"][:, idx_t].t()
+        return q.double().cpu().numpy(), u.double().cpu().numpy()
+
+    Q64, U64 = rows(subt)
+    t0 = time.perf_counter()
+    rq, ru = oracle.fdf(Q64, U64, lam, w, phi, layout=0)
+    done_los = len(sub)
+    elapsed = time.perf_counter() - t0
+    # keep going on further chunks of the cube until the time budget is used
+    chunk = len(sub)
+    start = 0
+    while elapsed < seconds and start + chunk <= cube["nlos"]:
+        q, u = rows(torch.arange(start, start + chunk, device="cuda"))
+        t1 = time.perf_counter()
+        oracle.fdf(q, u, lam, w, phi, layout=0)
+        elapsed += time.perf_counter() - t1
+        done_los += chunk
+        start += chunk
+    samples = done_los * len(lam) * len(phi)
+    ref = oracle.peaks(rq, ru, phi)
+    errors = {}
+    for name, (Fq, Fu, idx) in gpu_out.items():
+        gq, gu = Fq[subt].cpu().numpy(), Fu[subt].cpu().numpy()
+        e = oracle.per_los_error(gq, gu, rq, ru)
+        nun, mism, bad = oracle.peak_agreement(idx[subt].cpu().numpy(), rq, ru, ref)
+        errors[name] = {"max_per_los_rel_err": float(e.max()), "median_per_los_rel_err": float(np.median(e)),
+                        "peaks_unambiguous": nun, "peak_mismatches": mism, "ambiguous_invalid": bad,
+                        "subsample_los": int(len(sub))}
+    return ({"value": samples / elapsed / 1e9, "unit": "Gsamples/s", "cores": oracle.threads(),
+             "kind": "oracle",
+             "sample": f"{done_los} LOS x {len(lam)} channels x {len(phi)} phi "
+                       f"(stratified 2048 source + 2048 noise LOS, then contiguous chunks), "
+                       f"FP64 table-mode C triple loop, {elapsed:.1f} s"}, errors)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this RM-synthesis build measures one GPU only; "
+                                   "run with --gpus 1 (LOS sharding across GPUs is a design note)"}))
+        return 2
+    import torch
+    import paper_1810_06250_amd as rs
+    from synthetic import WORKLOADS, make_cube, stratified_subsample
+
+    wl = WORKLOADS[args.workload]
+    log(f"generating {args.workload}: {wl.nlos} LOS x {wl.nchan} ch x {len(wl.phi())} phi")
+    cube = make_cube(wl, device="cuda")
+    plan = rs.Plan(cube["lambda2"], cube["weights"], cube["phi"])
+    nlos, nchan, nphi = cube["nlos"], len(cube["lambda2"]), len(cube["phi"])
+    samples = nlos * nchan * nphi
+
+    def alloc():
+        Fq = torch.empty((nlos, nphi), dtype=torch.float32, device="cuda")
+        Fu = torch.empty_like(Fq)
+        pk = dict(idx=torch.empty(nlos, dtype=torch.int32, device="cuda"),
+                  phi_pk=torch.empty(nlos, device="cuda"), amp=torch.empty(nlos, device="cuda"),
+                  q_pk=torch.empty(nlos, device="cuda"), u_pk=torch.empty(nlos, device="cuda"))
+        return Fq, Fu, pk
+
+    prec_id = rs.PRECISIONS[args.precision]
+    Fq, Fu, pk = alloc()
+    log(f"timing {args.precision}: {args.warmup} warmup + {args.steps} steps")
+    wall, ex_ms, pk_ms = time_path(rs, plan, cube, prec_id, Fq, Fu, pk, args.steps, args.warmup)
+    gpu_out = {args.precision: (Fq, Fu, pk["idx"])}
+
+    fp32 = None
+    if args.precision != "fp32" and not args.no_fp32_compare:
+        Fq2, Fu2, pk2 = alloc()
+        steps32 = max(3, args.steps // 4)
+        log(f"timing fp32 path: 1 warmup + {steps32} steps")
+        w32, ex32, pk32 = time_path(rs, plan, cube, rs.RMSYNTH_FP32, Fq2, Fu2, pk2, steps32, 1)
+        gpu_out["fp32"] = (Fq2, Fu2, pk2["idx"])
+        fp32 = {"value": samples / (w32 * 1e-3) / 1e9, "unit": "Gsamples/s", "ms_per_step": w32,
+                "execute_ms": ex32, "peaks_ms": pk32,
+                "mfma_tflops": 8.0 * samples / (ex32 * 1e-3) / 1e12,
+                "frac_fp32_peak": 8.0 * samples / (ex32 * 1e-3) / 1e12 / MFMA_PEAK_TFLOPS["fp32"]}
+
+    achieved = MFMA_FLOP_PER_SAMPLE[args.precision] * samples / (ex_ms * 1e-3) / 1e12
+    peak = MFMA_PEAK_TFLOPS[args.precision]
+    res = {
+        "metric": METRIC,
+        "value": samples / (wall * 1e-3) / 1e9,
+        "unit": "Gsamples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16" if args.precision == "bf16x3" else "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {wl.nx}x{wl.ny} LOS, {nchan} channels "
+                               f"{wl.f_lo:g}-{wl.f_hi:g} MHz, phi {wl.phi_lo:g}..{wl.phi_hi:g} "
+                               f"step {wl.phi_step:g} ({nphi}), "
+                               f"{'LOS-major' if cube['layout'] == 0 else 'frequency-major'}",
+                   "nlos": nlos, "nchan": nchan, "nphi": nphi, "samples": samples,
+                   "precision": args.precision,
+                   "step": "rmsynth_execute + rmsynth_peaks"},
+        "kernels": {"execute_ms": ex_ms, "peaks_ms": pk_ms,
+                    "peaks_hbm_gbs": 8.0 * nlos * nphi / (pk_ms * 1e-3) / 1e9},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "per_unit": f"{MFMA_FLOP_PER_SAMPLE[args.precision]:g} MFMA flop per "
+                                 f"LOS*channel*phi sample x {samples} samples per launch"},
+        "effective_fp32_tflops": 8.0 * samples / (ex_ms * 1e-3) / 1e12,
+    }
+    if fp32 is not None:
+        res["fp32_path"] = fp32
+        res["speedup_vs_fp32_execute"] = fp32["execute_ms"] / ex_ms
+    if not args.no_cpu_baseline:
+        sub = stratified_subsample(nlos, cube["src_los"], 4096, seed=wl.seed + 11)
+        log("cpu_baseline: FP64 oracle on host cores")
+        cb, errors = cpu_baseline_leg(cube, sub, gpu_out, args.cpu_seconds)
+        res["cpu_baseline"] = cb
+        res["errors_vs_oracle"] = errors
+    print(json.dumps(res), flush=True)
+    plan.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

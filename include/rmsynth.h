@@ -1,0 +1,167 @@
+/*
+ * rmsynth.h -- C ABI of the MI355X (gfx950) RM-synthesis library librmsynth.so.
+ *
+ * The library evaluates the discrete Faraday-depth transform of rotation
+ * measure synthesis (Sridhar, Heald & van der Hulst, "cuFFS", Section 2.2):
+ *
+ *   F_l(phi_k) = K sum_j w_j (Q_lj + i U_lj) exp(-2 i phi_k (lambda_j^2 - lambda0^2))
+ *                                                                    eq. (11)
+ *   K = 1 / sum_j w_j                                                eq. (13)
+ *   Re F = Qt, Im F = Ut                                         eqs. (15)-(16)
+ *   |F| = sqrt(Qt^2 + Ut^2)                                          eq. (17)
+ *
+ * for every line of sight (LOS) l of a Q/U cube and every phi_k of a grid
+ * (eqs. (18)-(19)), together with the RM spread function R(phi), eq. (12),
+ * and the per-LOS peak of |F| (phi_peak, |F|max, Qt and Ut at the peak).
+ *
+ * Conventions shared by every call
+ *   - Return value: RMSYNTH_OK (0) or a negative rmsynth_status.  The reason
+ *     of the last failure on the calling thread is in rmsynth_last_error().
+ *   - Argument errors are detected and returned before anything is enqueued.
+ *   - Device buffers are plain device pointers (e.g. from hipMalloc or a torch
+ *     tensor's data pointer) owned by the caller; the library never frees or
+ *     keeps them.  Host arrays passed to rmsynth_plan are copied.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Work
+ *     is enqueued asynchronously on it; nothing synchronises.  A fault inside a
+ *     kernel surfaces as RMSYNTH_EHIP from a later call or synchronisation.
+ *   - A plan belongs to the device that was current when it was created; it
+ *     must be used with that device current.  A plan is immutable after
+ *     creation and may be used concurrently from several streams.
+ *   - Output layout is phi-fastest: Fq[l * nphi + k].
+ */
+#ifndef RMSYNTH_H
+#define RMSYNTH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rmsynth_plan_s* rmsynth_plan_t;
+
+typedef enum {
+    RMSYNTH_OK = 0,
+    RMSYNTH_EINVAL = -1,        /* invalid argument                          */
+    RMSYNTH_ENOMEM = -2,        /* device or host allocation failed          */
+    RMSYNTH_EHIP = -3,          /* a HIP runtime call or kernel launch failed */
+    RMSYNTH_EUNSUPPORTED = -4,  /* valid but not supported combination      */
+    RMSYNTH_EWORKSPACE = -5     /* workspace too small                       */
+} rmsynth_status;
+
+typedef enum {
+    RMSYNTH_LOS_MAJOR = 0,   /* Q[l * nchan + j]: frequency fastest            */
+    RMSYNTH_FREQ_MAJOR = 1   /* Q[j * nlos + l]: LOS fastest (channel planes)  */
+} rmsynth_layout;
+
+typedef enum {
+    RMSYNTH_FP32 = 0,        /* FP32 products, FP32 accumulation (FP32 MFMA)     */
+    RMSYNTH_SPLIT_BF16 = 1,  /* x = hi + lo in bfloat16; hi*hi + hi*lo + lo*hi
+                                on BF16 MFMA with FP32 accumulation             */
+    RMSYNTH_SPLIT_FP16 = 2   /* same split in IEEE half precision               */
+} rmsynth_precision;
+
+/*
+ * rmsynth_plan -- prepare the channel set and the Faraday-depth grid.
+ * Passage: eqs. (11)-(13) and the definition of lambda0^2 (Section 2.2);
+ * K, 2 phi and lambda^2 - lambda0^2 are computed once per data set
+ * (Section 2.3).
+ *   lambda2  [nchan] host, lambda_j^2 in m^2, finite.
+ *   weights  [nchan] host, w_j >= 0 and finite; w_j = 0 flags channel j (its
+ *            Q/U values, NaN included, then have no effect).  sum w > 0.
+ *   phi      [nphi]  host, Faraday depths in rad m^-2, finite, any order.
+ *   lambda0_sq  reference lambda^2; NaN selects the weighted mean
+ *            K sum_j w_j lambda_j^2.
+ *   out      receives the plan (destroy with rmsynth_destroy).
+ * Limits: 1 <= nchan <= 65536, 1 <= nphi <= 1048576.
+ * K and lambda0^2 are formed in FP64 on the host; the plan uploads the
+ * FP64 tables the GPU phase generator needs (a few tens of KB).
+ * Errors: EINVAL (bad sizes / values / NULL), ENOMEM, EHIP.
+ */
+int rmsynth_plan(const double* lambda2, const double* weights, int32_t nchan,
+                 const double* phi, int32_t nphi, double lambda0_sq,
+                 rmsynth_plan_t* out);
+
+/*
+ * rmsynth_plan_info -- scalars of a plan (any pointer may be NULL).
+ *   K           eq. (13).
+ *   lambda0_sq  the reference lambda^2 in use.
+ *   fwhm_est    2 sqrt(3) / Delta lambda^2, eq. (20), Delta lambda^2 = span of
+ *               lambda^2 over channels of non-zero weight.
+ *   phimax_est  sqrt(3) / delta lambda^2, eq. (21), delta lambda^2 = widest gap
+ *               between adjacent channel centres (all channels).
+ *   nchan, nphi sizes of the plan.
+ */
+int rmsynth_plan_info(rmsynth_plan_t plan, double* K, double* lambda0_sq,
+                      double* fwhm_est, double* phimax_est,
+                      int32_t* nchan, int32_t* nphi);
+
+/*
+ * rmsynth_workspace_size -- device workspace rmsynth_execute needs for `nlos`
+ * LOS in the given layout and precision.  The current kernels read Q/U in
+ * place and need none (*bytes = 0); the argument pair exists so that callers
+ * stay valid when a path gains one.
+ */
+int rmsynth_workspace_size(rmsynth_plan_t plan, int64_t nlos, int32_t layout,
+                           int32_t precision, size_t* bytes);
+
+/*
+ * rmsynth_rmsf -- the RM spread function on the plan's grid, eq. (12):
+ *   R(phi_k) = K sum_j w_j exp(-2 i phi_k (lambda_j^2 - lambda0^2)).
+ *   R_re, R_im  [nphi] device float, written.
+ * FP64 argument reduction, FP32 sin/cos and accumulation.
+ */
+int rmsynth_rmsf(rmsynth_plan_t plan, float* R_re, float* R_im, void* stream);
+
+/*
+ * rmsynth_execute -- the Faraday-depth transform, eqs. (11), (15)-(17), for
+ * nlos lines of sight.
+ *   Q, U     device float, layout RMSYNTH_LOS_MAJOR: [nlos][nchan];
+ *            RMSYNTH_FREQ_MAJOR: [nchan][nlos].  Read only.
+ *   nlos     >= 0 (0 enqueues nothing).
+ *   precision  rmsynth_precision.
+ *   Fq, Fu   [nlos][nphi] device float, written: Re F and Im F.
+ *   Fabs     [nlos][nphi] device float or NULL: |F| when non-NULL.
+ *   workspace, workspace_bytes: device scratch of at least
+ *            rmsynth_workspace_size() bytes (may be NULL when that is 0).
+ * A LOS whose unflagged channels hold a non-finite value gets non-finite
+ * outputs; other LOS are unaffected.
+ * Errors: EINVAL (NULL buffers with nlos > 0, bad layout/precision, wrong
+ * device current), EWORKSPACE, EHIP (launch failure).
+ */
+int rmsynth_execute(rmsynth_plan_t plan, const float* Q, const float* U, int64_t nlos,
+                    int32_t layout, int32_t precision,
+                    float* Fq, float* Fu, float* Fabs,
+                    void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * rmsynth_peaks -- per-LOS peak of |F| (the Faraday depth phi_peak where |F|
+ * is largest, Section 2.2 after eq. (14)).
+ *   Fq, Fu   [nlos][nphi] device float (as written by rmsynth_execute).
+ *   idx      [nlos] device int32: smallest k maximising Fq^2 + Fu^2 (FP32);
+ *            -1 if any |F| of that LOS is non-finite.
+ *   phi_pk   [nlos] device float: phi[idx] (NaN when idx = -1).
+ *   amp      [nlos] device float: |F| at idx.
+ *   q_pk, u_pk [nlos] device float: Fq, Fu at idx.  Any of the five outputs
+ *            except idx may be NULL.
+ */
+int rmsynth_peaks(rmsynth_plan_t plan, const float* Fq, const float* Fu, int64_t nlos,
+                  int32_t* idx, float* phi_pk, float* amp, float* q_pk, float* u_pk,
+                  void* stream);
+
+/* rmsynth_destroy -- free a plan's device tables (NULL is a no-op).  The caller
+ * must make sure no enqueued work still uses the plan. */
+void rmsynth_destroy(rmsynth_plan_t plan);
+
+/* rmsynth_last_error -- message of the last failure on this thread ("" if none). */
+const char* rmsynth_last_error(void);
+
+/* rmsynth_version -- library version string. */
+const char* rmsynth_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RMSYNTH_H */

@@ -9,6 +9,7 @@ from .oracle import (  # noqa: F401
     plan,
     plan_info,
     cost_flop,
+    threads,
     fdf,
     rmsf,
     peaks,

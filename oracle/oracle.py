@@ -56,6 +56,8 @@ def _load():
         lib.oracle_rmsf.restype = ctypes.c_int
         lib.oracle_peaks.argtypes = [P, P, i64, i32, P, P, P, P, P, P, P]
         lib.oracle_peaks.restype = ctypes.c_int
+        lib.oracle_threads.argtypes = []
+        lib.oracle_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -86,6 +88,11 @@ def plan_info(lambda2, w):
     if _load().oracle_plan_info(_ptr(lam), _ptr(w), lam.size, ctypes.byref(a), ctypes.byref(b)):
         raise ValueError("oracle_plan_info failed")
     return a.value, b.value
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's loops run on."""
+    return int(_load().oracle_threads())
 
 
 def cost_flop(nlos, nchan, nphi) -> float:

@@ -216,3 +216,16 @@ int oracle_peaks(const double* Fq, const double* Fu, int64_t nlos, int32_t nphi,
     }
     return 0;
 }
+
+/* Number of OpenMP threads the parallel loops above use. */
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+int oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -1,0 +1,235 @@
+// C ABI of librmsynth: plan construction, validation and dispatch.
+// The arithmetic of the method runs in the HIP kernels; the host forms K and
+// lambda0^2 in FP64 (eq. (13)) and uploads the phase-generator tables.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int ok()
+{
+    g_last_error.clear();
+    return RMSYNTH_OK;
+}
+
+int hip_fail(hipError_t e, const char* what)
+{
+    return fail(RMSYNTH_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+void free_plan(rmsynth_plan_s* p)
+{
+    if (!p) return;
+    if (p->d_b) (void)hipFree(p->d_b);
+    if (p->d_w) (void)hipFree(p->d_w);
+    if (p->d_phi) (void)hipFree(p->d_phi);
+    delete p;
+}
+
+int check_device(const rmsynth_plan_s* p)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev != p->device)
+        return fail(RMSYNTH_EINVAL, "plan was created on device %d but device %d is current",
+                    p->device, dev);
+    return RMSYNTH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rmsynth_last_error(void) { return g_last_error.c_str(); }
+
+const char* rmsynth_version(void) { return "rmsynth-gfx950 0.1"; }
+
+int rmsynth_plan(const double* lambda2, const double* weights, int32_t nchan, const double* phi,
+                 int32_t nphi, double lambda0_sq, rmsynth_plan_t* out)
+{
+    if (!out) return fail(RMSYNTH_EINVAL, "rmsynth_plan: out is NULL");
+    *out = nullptr;
+    if (!lambda2 || !weights || !phi) return fail(RMSYNTH_EINVAL, "rmsynth_plan: NULL array");
+    if (nchan < 1 || nchan > 65536) return fail(RMSYNTH_EINVAL, "rmsynth_plan: nchan=%d", nchan);
+    if (nphi < 1 || nphi > (1 << 20)) return fail(RMSYNTH_EINVAL, "rmsynth_plan: nphi=%d", nphi);
+    double sw = 0.0, swl = 0.0, lo = INFINITY, hi = -INFINITY;
+    for (int32_t j = 0; j < nchan; ++j) {
+        const double w = weights[j], l = lambda2[j];
+        if (!std::isfinite(w) || w < 0.0)
+            return fail(RMSYNTH_EINVAL, "rmsynth_plan: weight %d is %g", j, w);
+        if (!std::isfinite(l)) return fail(RMSYNTH_EINVAL, "rmsynth_plan: lambda2 %d is %g", j, l);
+        sw += w;
+        swl += w * l;
+        if (w > 0.0) { lo = std::min(lo, l); hi = std::max(hi, l); }
+    }
+    if (!(sw > 0.0)) return fail(RMSYNTH_EINVAL, "rmsynth_plan: sum of weights is %g", sw);
+    for (int32_t k = 0; k < nphi; ++k)
+        if (!std::isfinite(phi[k])) return fail(RMSYNTH_EINVAL, "rmsynth_plan: phi %d is %g", k, phi[k]);
+    if (!std::isnan(lambda0_sq) && !std::isfinite(lambda0_sq))
+        return fail(RMSYNTH_EINVAL, "rmsynth_plan: lambda0_sq is %g", lambda0_sq);
+
+    auto* p = new (std::nothrow) rmsynth_plan_s{};
+    if (!p) return fail(RMSYNTH_ENOMEM, "rmsynth_plan: host allocation");
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) { free_plan(p); return hip_fail(e, "hipGetDevice"); }
+    p->nchan = nchan;
+    p->nphi = nphi;
+    p->nchan_pad = (int32_t)round_up(nchan, kChanPad);
+    p->nphi_pad = (int32_t)round_up(nphi, kPhiPad);
+    p->K = 1.0 / sw;
+    p->lambda0_sq = std::isnan(lambda0_sq) ? p->K * swl : lambda0_sq;
+    p->fwhm_est = hi > lo ? 2.0 * std::sqrt(3.0) / (hi - lo) : INFINITY;
+    std::vector<double> sorted(lambda2, lambda2 + nchan);
+    std::sort(sorted.begin(), sorted.end());
+    double gap = 0.0;
+    for (int32_t j = 1; j < nchan; ++j) gap = std::max(gap, sorted[j] - sorted[j - 1]);
+    p->phimax_est = gap > 0.0 ? std::sqrt(3.0) / gap : INFINITY;
+
+    std::vector<double> hb(p->nchan_pad, 0.0), hphi(p->nphi_pad, 0.0);
+    std::vector<float> hw(p->nchan_pad, 0.0f);
+    for (int32_t j = 0; j < nchan; ++j) {
+        hb[j] = (lambda2[j] - p->lambda0_sq) / M_PI;
+        hw[j] = (float)weights[j];
+    }
+    std::copy(phi, phi + nphi, hphi.begin());
+
+    if ((e = hipMalloc(&p->d_b, sizeof(double) * p->nchan_pad)) != hipSuccess ||
+        (e = hipMalloc(&p->d_w, sizeof(float) * p->nchan_pad)) != hipSuccess ||
+        (e = hipMalloc(&p->d_phi, sizeof(double) * p->nphi_pad)) != hipSuccess) {
+        free_plan(p);
+        return fail(RMSYNTH_ENOMEM, "rmsynth_plan: hipMalloc: %s", hipGetErrorString(e));
+    }
+    if ((e = hipMemcpy(p->d_b, hb.data(), sizeof(double) * p->nchan_pad, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(p->d_w, hw.data(), sizeof(float) * p->nchan_pad, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(p->d_phi, hphi.data(), sizeof(double) * p->nphi_pad, hipMemcpyHostToDevice)) != hipSuccess) {
+        free_plan(p);
+        return hip_fail(e, "rmsynth_plan: hipMemcpy");
+    }
+    *out = p;
+    return ok();
+}
+
+int rmsynth_plan_info(rmsynth_plan_t p, double* K, double* lambda0_sq, double* fwhm_est,
+                      double* phimax_est, int32_t* nchan, int32_t* nphi)
+{
+    if (!p) return fail(RMSYNTH_EINVAL, "rmsynth_plan_info: plan is NULL");
+    if (K) *K = p->K;
+    if (lambda0_sq) *lambda0_sq = p->lambda0_sq;
+    if (fwhm_est) *fwhm_est = p->fwhm_est;
+    if (phimax_est) *phimax_est = p->phimax_est;
+    if (nchan) *nchan = p->nchan;
+    if (nphi) *nphi = p->nphi;
+    return ok();
+}
+
+int rmsynth_workspace_size(rmsynth_plan_t p, int64_t nlos, int32_t layout, int32_t precision,
+                           size_t* bytes)
+{
+    if (!p || !bytes) return fail(RMSYNTH_EINVAL, "rmsynth_workspace_size: NULL argument");
+    if (nlos < 0) return fail(RMSYNTH_EINVAL, "rmsynth_workspace_size: nlos=%lld", (long long)nlos);
+    if (layout != RMSYNTH_LOS_MAJOR && layout != RMSYNTH_FREQ_MAJOR)
+        return fail(RMSYNTH_EINVAL, "rmsynth_workspace_size: layout=%d", layout);
+    if (precision < RMSYNTH_FP32 || precision > RMSYNTH_SPLIT_FP16)
+        return fail(RMSYNTH_EINVAL, "rmsynth_workspace_size: precision=%d", precision);
+    *bytes = 0;
+    return ok();
+}
+
+int rmsynth_rmsf(rmsynth_plan_t p, float* R_re, float* R_im, void* stream)
+{
+    if (!p || !R_re || !R_im) return fail(RMSYNTH_EINVAL, "rmsynth_rmsf: NULL argument");
+    if (int rc = check_device(p)) return rc;
+    hipError_t e = launch_rmsf(*p, R_re, R_im, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "rmsynth_rmsf launch");
+    return ok();
+}
+
+int rmsynth_execute(rmsynth_plan_t p, const float* Q, const float* U, int64_t nlos, int32_t layout,
+                    int32_t precision, float* Fq, float* Fu, float* Fabs, void* workspace,
+                    size_t workspace_bytes, void* stream)
+{
+    (void)workspace;
+    (void)workspace_bytes;
+    if (!p) return fail(RMSYNTH_EINVAL, "rmsynth_execute: plan is NULL");
+    if (nlos < 0) return fail(RMSYNTH_EINVAL, "rmsynth_execute: nlos=%lld", (long long)nlos);
+    if (layout != RMSYNTH_LOS_MAJOR && layout != RMSYNTH_FREQ_MAJOR)
+        return fail(RMSYNTH_EINVAL, "rmsynth_execute: layout=%d", layout);
+    if (precision < RMSYNTH_FP32 || precision > RMSYNTH_SPLIT_FP16)
+        return fail(RMSYNTH_EINVAL, "rmsynth_execute: precision=%d", precision);
+    if (nlos == 0) return ok();
+    if (!Q || !U || !Fq || !Fu) return fail(RMSYNTH_EINVAL, "rmsynth_execute: NULL buffer");
+    if (precision == RMSYNTH_SPLIT_FP16)
+        return fail(RMSYNTH_EUNSUPPORTED, "rmsynth_execute: FP16 split is not available yet");
+    if (int rc = check_device(p)) return rc;
+
+    // Launch in LOS batches so that one grid stays below kMaxBlocks.
+    const int64_t tiles_n = (p->nphi + 127) / 128;
+    const int64_t max_los = std::max<int64_t>(128, kMaxBlocks / tiles_n * 64);
+    for (int64_t l0 = 0; l0 < nlos;) {
+        const int64_t n = std::min(nlos - l0, max_los);
+        ExecArgs a{};
+        if (layout == RMSYNTH_LOS_MAJOR) {
+            a.Q = Q + l0 * p->nchan;
+            a.U = U + l0 * p->nchan;
+            a.ld = p->nchan;
+            a.vec4 = (p->nchan % 4 == 0) && ((uintptr_t)Q % 16 == 0) && ((uintptr_t)U % 16 == 0);
+        } else {
+            a.Q = Q + l0;
+            a.U = U + l0;
+            a.ld = nlos;
+            a.vec4 = false;
+        }
+        a.nlos = n;
+        a.layout = layout;
+        a.Fq = Fq + l0 * p->nphi;
+        a.Fu = Fu + l0 * p->nphi;
+        a.Fabs = Fabs ? Fabs + l0 * p->nphi : nullptr;
+        a.stream = (hipStream_t)stream;
+        hipError_t e = precision == RMSYNTH_FP32 ? launch_synth_fp32(*p, a)
+                                                 : launch_synth_split(*p, a, precision);
+        if (e != hipSuccess) return hip_fail(e, "rmsynth_execute launch");
+        l0 += n;
+    }
+    return ok();
+}
+
+int rmsynth_peaks(rmsynth_plan_t p, const float* Fq, const float* Fu, int64_t nlos, int32_t* idx,
+                  float* phi_pk, float* amp, float* q_pk, float* u_pk, void* stream)
+{
+    if (!p) return fail(RMSYNTH_EINVAL, "rmsynth_peaks: plan is NULL");
+    if (nlos < 0) return fail(RMSYNTH_EINVAL, "rmsynth_peaks: nlos=%lld", (long long)nlos);
+    if (nlos == 0) return ok();
+    if (!Fq || !Fu || !idx) return fail(RMSYNTH_EINVAL, "rmsynth_peaks: NULL buffer");
+    if (int rc = check_device(p)) return rc;
+    hipError_t e = launch_peaks(*p, Fq, Fu, nlos, idx, phi_pk, amp, q_pk, u_pk, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "rmsynth_peaks launch");
+    return ok();
+}
+
+void rmsynth_destroy(rmsynth_plan_t p) { free_plan(p); }
+
+}  // extern "C"

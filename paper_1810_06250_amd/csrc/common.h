@@ -1,0 +1,144 @@
+// Shared device helpers and the host-side plan of librmsynth (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rmsynth.h"
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x8_t __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// Plan (host object).  The device tables are padded so that kernels can read
+// whole channel steps and whole phi tiles without bounds checks:
+//   d_b   [nchan_pad]  FP64 (lambda_j^2 - lambda0^2) / pi; 0 in the padding,
+//                      so that 2 phi (lambda^2 - lambda0^2) = 2 pi phi b
+//   d_w   [nchan_pad]  FP32 w_j; 0 in the padding (= flagged)
+//   d_phi [nphi_pad]   FP64 phi_k; 0 in the padding
+// ---------------------------------------------------------------------------
+struct rmsynth_plan_s {
+    int device;
+    int32_t nchan, nphi, nchan_pad, nphi_pad;
+    double K, lambda0_sq, fwhm_est, phimax_est;
+    double* d_b;
+    float* d_w;
+    double* d_phi;
+};
+
+constexpr int kChanPad = 32;    // channel padding granule (largest K-step)
+constexpr int kPhiPad = 256;    // phi padding granule (largest phi tile)
+
+// ---------------------------------------------------------------------------
+// Phase generator.  theta = 2 phi a = 2 pi t with t = phi * (a / pi) in
+// revolutions.  The reduction runs in FP64: q = nearest quarter turn,
+// f = t - q/4 (exact, |f| <= 1/8), x = 2 pi f in [-pi/4, pi/4], rounded once
+// to FP32.  sin x and cos x are the Taylor series of the functions with exact
+// reciprocal-factorial coefficients, truncated after x^9 and x^10, whose
+// truncation error on [-pi/4, pi/4] is below 2e-9 (under half an FP32 ulp);
+// the quarter-turn index then selects sign and swap.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void phase_cos_sin(double t, float& c, float& s)
+{
+    const double q = __builtin_rint(4.0 * t);
+    const double f = __builtin_fma(q, -0.25, t);
+    const float x = (float)(f * 6.283185307179586476925286766559);
+    const int n = (int)q & 3;
+    const float x2 = x * x;
+    float sp = 1.0f / 362880.0f;
+    sp = __builtin_fmaf(sp, x2, -1.0f / 5040.0f);
+    sp = __builtin_fmaf(sp, x2, 1.0f / 120.0f);
+    sp = __builtin_fmaf(sp, x2, -1.0f / 6.0f);
+    sp = __builtin_fmaf(sp * x2, x, x);
+    float cp = -1.0f / 3628800.0f;
+    cp = __builtin_fmaf(cp, x2, 1.0f / 40320.0f);
+    cp = __builtin_fmaf(cp, x2, -1.0f / 720.0f);
+    cp = __builtin_fmaf(cp, x2, 1.0f / 24.0f);
+    cp = __builtin_fmaf(cp, x2, -0.5f);
+    cp = __builtin_fmaf(cp, x2, 1.0f);
+    const float cc = (n & 1) ? sp : cp;
+    const float ss = (n & 1) ? cp : sp;
+    c = ((n + 1) & 2) ? -cc : cc;
+    s = (n & 2) ? -ss : ss;
+}
+
+// ---------------------------------------------------------------------------
+// hi/lo splits.  x = hi + lo + r with hi = RNE(x), lo = RNE(x - hi) in the
+// 16-bit format; x - hi is exact in FP32.  Pairs are packed into one dword,
+// first element in the low half (the lower MFMA k slot).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t pack2_bf16(float a, float b)
+{
+    bf16x2_t v = {(__bf16)a, (__bf16)b};
+    return __builtin_bit_cast(uint32_t, v);
+}
+
+__device__ __forceinline__ void split2_bf16(float a, float b, uint32_t& hi, uint32_t& lo)
+{
+    hi = pack2_bf16(a, b);
+    const float ra = a - __uint_as_float(hi << 16);
+    const float rb = b - __uint_as_float(hi & 0xffff0000u);
+    lo = pack2_bf16(ra, rb);
+}
+
+__device__ __forceinline__ uint32_t pack2_f16(float a, float b)
+{
+    f16x2_t v = {(_Float16)a, (_Float16)b};
+    return __builtin_bit_cast(uint32_t, v);
+}
+
+__device__ __forceinline__ void split2_f16(float a, float b, uint32_t& hi, uint32_t& lo)
+{
+    hi = pack2_f16(a, b);
+    f16x2_t h = __builtin_bit_cast(f16x2_t, hi);
+    lo = pack2_f16(a - (float)h[0], b - (float)h[1]);
+}
+
+// (x, y) packed -> (y, -x) packed: the imaginary-part row of the real form.
+// Flipping the sign bit of a 16-bit float is exact in both formats.
+__device__ __forceinline__ uint32_t swap_negate(uint32_t d)
+{
+    return (d >> 16) | ((d ^ 0x8000u) << 16);
+}
+
+// Map a hardware workgroup id to a logical tile so that logical neighbours
+// (the phi tiles of one LOS tile, which read the same Q/U rows) run on the
+// same XCD: workgroups are dispatched round-robin over the 8 XCDs, each with
+// its own L2.
+__device__ __forceinline__ int64_t xcd_tile(int64_t bid, int64_t nblk)
+{
+    const int64_t per = nblk >> 3;
+    if (bid < (per << 3)) return (bid & 7) * per + (bid >> 3);
+    return bid;
+}
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (one per translation unit).  Each returns a hipError_t.
+// ---------------------------------------------------------------------------
+struct ExecArgs {
+    const float* Q;
+    const float* U;
+    int64_t nlos;      // LOS in this launch
+    int64_t ld;        // LOS-major: row stride (nchan); freq-major: plane stride
+    int layout;
+    bool vec4;         // 16-byte loads allowed
+    float* Fq;
+    float* Fu;
+    float* Fabs;
+    hipStream_t stream;
+};
+
+hipError_t launch_synth_fp32(const rmsynth_plan_s& p, const ExecArgs& a);
+hipError_t launch_synth_split(const rmsynth_plan_s& p, const ExecArgs& a, int precision);
+hipError_t launch_peaks(const rmsynth_plan_s& p, const float* Fq, const float* Fu, int64_t nlos,
+                        int32_t* idx, float* phi_pk, float* amp, float* q_pk, float* u_pk,
+                        hipStream_t s);
+hipError_t launch_rmsf(const rmsynth_plan_s& p, float* re, float* im, hipStream_t s);
+
+// Largest number of workgroups one launch may use (grid x dimension limit,
+// kept well inside 2^31 - 1).
+constexpr int64_t kMaxBlocks = int64_t(1) << 30;

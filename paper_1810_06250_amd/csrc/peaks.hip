@@ -1,0 +1,123 @@
+// Per-LOS peak of |F| and the RM spread function.
+//
+// Peaks: one wave64 per LOS.  Each lane scans phi k = lane, lane + 64, ...
+// keeping the largest Fq^2 + Fu^2 (strict >, so its lowest k), then a
+// butterfly of cross-lane shuffles merges (value, index) pairs, ties going to
+// the lower index.  Any non-finite Fq or Fu marks the LOS (idx = -1).
+// HBM-bound: 8 bytes read per (LOS, phi).
+//
+// RMSF, eq. (12): one thread per phi, FP64 argument reduction and FP32
+// sin/cos (the same generator as the transform), FP32 accumulation.
+#include <float.h>
+
+#include "common.h"
+
+namespace {
+
+constexpr int WAVES = 4;
+
+__global__ __launch_bounds__(256) void peaks_kernel(
+    const float* __restrict__ Fq, const float* __restrict__ Fu, int64_t nlos, int nphi,
+    const double* __restrict__ phik, int32_t* __restrict__ idx, float* __restrict__ phi_pk,
+    float* __restrict__ amp, float* __restrict__ q_pk, float* __restrict__ u_pk)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t l = (int64_t)blockIdx.x * WAVES + (threadIdx.x >> 6);
+    if (l >= nlos) return;  // uniform per wave
+    const float* q = Fq + l * nphi;
+    const float* u = Fu + l * nphi;
+    float best = -1.0f;
+    int bi = 0x7fffffff;
+    bool bad = false;
+    int k = lane;
+    for (; k + 192 < nphi; k += 256) {
+        float a[4], b[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) { a[i] = q[k + 64 * i]; b[i] = u[k + 64 * i]; }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            bad |= !(__builtin_fabsf(a[i]) <= FLT_MAX) || !(__builtin_fabsf(b[i]) <= FLT_MAX);
+            const float m = a[i] * a[i] + b[i] * b[i];
+            if (m > best) { best = m; bi = k + 64 * i; }
+        }
+    }
+    for (; k < nphi; k += 64) {
+        const float a = q[k], b = u[k];
+        bad |= !(__builtin_fabsf(a) <= FLT_MAX) || !(__builtin_fabsf(b) <= FLT_MAX);
+        const float m = a * a + b * b;
+        if (m > best) { best = m; bi = k; }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const float ob = __shfl_xor(best, off, 64);
+        const int oi = __shfl_xor(bi, off, 64);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    }
+    const bool anybad = __any(bad);
+    if (lane == 0) {
+        if (anybad || bi < 0 || bi >= nphi) {
+            idx[l] = -1;
+            const float nan = __builtin_nanf("");
+            if (phi_pk) phi_pk[l] = nan;
+            if (amp) amp[l] = nan;
+            if (q_pk) q_pk[l] = nan;
+            if (u_pk) u_pk[l] = nan;
+        } else {
+            idx[l] = bi;
+            if (phi_pk) phi_pk[l] = (float)phik[bi];
+            if (amp) amp[l] = sqrtf(best);
+            if (q_pk) q_pk[l] = q[bi];
+            if (u_pk) u_pk[l] = u[bi];
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void rmsf_kernel(const double* __restrict__ bj,
+                                                   const float* __restrict__ wj, int nchan,
+                                                   const double* __restrict__ phik, int nphi,
+                                                   float K, float* __restrict__ re,
+                                                   float* __restrict__ im)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nphi) return;
+    const double ph = phik[k];
+    float sr = 0.0f, si = 0.0f;
+    for (int j = 0; j < nchan; ++j) {
+        const float w = wj[j];
+        if (w == 0.0f) continue;
+        float c, s;
+        phase_cos_sin(ph * bj[j], c, s);
+        sr = __builtin_fmaf(w, c, sr);
+        si = __builtin_fmaf(-w, s, si);
+    }
+    re[k] = K * sr;
+    im[k] = K * si;
+}
+
+}  // namespace
+
+hipError_t launch_peaks(const rmsynth_plan_s& p, const float* Fq, const float* Fu, int64_t nlos,
+                        int32_t* idx, float* phi_pk, float* amp, float* q_pk, float* u_pk,
+                        hipStream_t s)
+{
+    for (int64_t l0 = 0; l0 < nlos;) {
+        const int64_t n = std::min<int64_t>(nlos - l0, kMaxBlocks * WAVES);
+        const int64_t blocks = (n + WAVES - 1) / WAVES;
+        hipLaunchKernelGGL(peaks_kernel, dim3((unsigned)blocks), dim3(64 * WAVES), 0, s,
+                           Fq + l0 * p.nphi, Fu + l0 * p.nphi, n, p.nphi, p.d_phi, idx + l0,
+                           phi_pk ? phi_pk + l0 : nullptr, amp ? amp + l0 : nullptr,
+                           q_pk ? q_pk + l0 : nullptr, u_pk ? u_pk + l0 : nullptr);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        l0 += n;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_rmsf(const rmsynth_plan_s& p, float* re, float* im, hipStream_t s)
+{
+    const int blocks = (p.nphi + 255) / 256;
+    hipLaunchKernelGGL(rmsf_kernel, dim3(blocks), dim3(256), 0, s, p.d_b, p.d_w, p.nchan, p.d_phi,
+                       p.nphi, (float)p.K, re, im);
+    return hipGetLastError();
+}

@@ -1,0 +1,231 @@
+"""Python binding of librmsynth (argument marshalling only).
+
+The functions named like the C ABI (`rmsynth_plan`, `rmsynth_execute`, ...)
+take torch tensors for device buffers and numpy arrays for host arrays, pass
+their pointers and torch's current HIP stream, and raise `RmsynthError` on a
+non-zero status.  `Plan` is a small convenience wrapper over the same calls.
+
+Every step of the transform runs in the HIP library; if librmsynth.so is
+missing this module raises on import of the library, it never falls back.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "librmsynth.so")
+
+RMSYNTH_OK = 0
+RMSYNTH_EINVAL = -1
+RMSYNTH_ENOMEM = -2
+RMSYNTH_EHIP = -3
+RMSYNTH_EUNSUPPORTED = -4
+RMSYNTH_EWORKSPACE = -5
+
+RMSYNTH_LOS_MAJOR = 0
+RMSYNTH_FREQ_MAJOR = 1
+
+RMSYNTH_FP32 = 0
+RMSYNTH_SPLIT_BF16 = 1
+RMSYNTH_SPLIT_FP16 = 2
+
+PRECISIONS = {"fp32": RMSYNTH_FP32, "bf16x3": RMSYNTH_SPLIT_BF16, "fp16x3": RMSYNTH_SPLIT_FP16}
+LAYOUTS = {"los": RMSYNTH_LOS_MAJOR, "freq": RMSYNTH_FREQ_MAJOR}
+
+# (name, restype, argtypes) of every exported symbol.
+_P, _I32, _I64, _D, _SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+SIGNATURES = {
+    "rmsynth_plan": (ctypes.c_int, [_P, _P, _I32, _P, _I32, _D, ctypes.POINTER(_P)]),
+    "rmsynth_plan_info": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
+    "rmsynth_workspace_size": (ctypes.c_int, [_P, _I64, _I32, _I32, ctypes.POINTER(_SZ)]),
+    "rmsynth_rmsf": (ctypes.c_int, [_P, _P, _P, _P]),
+    "rmsynth_execute": (ctypes.c_int, [_P, _P, _P, _I64, _I32, _I32, _P, _P, _P, _P, _SZ, _P]),
+    "rmsynth_peaks": (ctypes.c_int, [_P, _P, _P, _I64, _P, _P, _P, _P, _P, _P]),
+    "rmsynth_destroy": (None, [_P]),
+    "rmsynth_last_error": (ctypes.c_char_p, []),
+    "rmsynth_version": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+class RmsynthError(RuntimeError):
+    def __init__(self, call: str, code: int, msg: str):
+        super().__init__(f"{call} failed with status {code}: {msg}")
+        self.code = code
+
+
+def load_library(path: str = LIB_PATH):
+    """Load librmsynth.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is missing: build it with "
+                               "`python -m paper_1810_06250_amd.build` (HIP, gfx950)")
+        lib = ctypes.CDLL(path)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(call: str, rc: int):
+    if rc != RMSYNTH_OK:
+        raise RmsynthError(call, rc, load_library().rmsynth_last_error().decode())
+
+
+def _stream(stream=None):
+    import torch
+    if stream is None:
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev(t, name, dtype=None):
+    """Device pointer of a contiguous CUDA tensor (None -> NULL)."""
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) torch tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _host64(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+# ------------------------------------------------------------------ C-ABI names
+def rmsynth_plan(lambda2, weights, phi, lambda0_sq: float = float("nan")) -> ctypes.c_void_p:
+    lam, w, ph = _host64(lambda2), _host64(weights), _host64(phi)
+    if lam.shape != w.shape:
+        raise ValueError("lambda2 and weights must have the same length")
+    h = ctypes.c_void_p()
+    _check("rmsynth_plan", load_library().rmsynth_plan(
+        lam.ctypes.data_as(_P), w.ctypes.data_as(_P), lam.size, ph.ctypes.data_as(_P), ph.size,
+        float(lambda0_sq), ctypes.byref(h)))
+    return h
+
+
+def rmsynth_plan_info(plan) -> dict:
+    K, l0, fw, pm = (ctypes.c_double() for _ in range(4))
+    nc, nphi = ctypes.c_int32(), ctypes.c_int32()
+    _check("rmsynth_plan_info", load_library().rmsynth_plan_info(
+        plan, ctypes.byref(K), ctypes.byref(l0), ctypes.byref(fw), ctypes.byref(pm),
+        ctypes.byref(nc), ctypes.byref(nphi)))
+    return dict(K=K.value, lambda0_sq=l0.value, fwhm_est=fw.value, phimax_est=pm.value,
+                nchan=nc.value, nphi=nphi.value)
+
+
+def rmsynth_workspace_size(plan, nlos: int, layout: int, precision: int) -> int:
+    b = ctypes.c_size_t()
+    _check("rmsynth_workspace_size", load_library().rmsynth_workspace_size(
+        plan, int(nlos), int(layout), int(precision), ctypes.byref(b)))
+    return b.value
+
+
+def rmsynth_rmsf(plan, R_re, R_im, stream=None):
+    import torch
+    _check("rmsynth_rmsf", load_library().rmsynth_rmsf(
+        plan, _dev(R_re, "R_re", torch.float32), _dev(R_im, "R_im", torch.float32), _stream(stream)))
+
+
+def rmsynth_execute(plan, Q, U, nlos: int, layout: int, precision: int, Fq, Fu, Fabs=None,
+                    workspace=None, workspace_bytes: int = 0, stream=None):
+    import torch
+    f32 = torch.float32
+    _check("rmsynth_execute", load_library().rmsynth_execute(
+        plan, _dev(Q, "Q", f32), _dev(U, "U", f32), int(nlos), int(layout), int(precision),
+        _dev(Fq, "Fq", f32), _dev(Fu, "Fu", f32), _dev(Fabs, "Fabs", f32),
+        _dev(workspace, "workspace"), int(workspace_bytes), _stream(stream)))
+
+
+def rmsynth_peaks(plan, Fq, Fu, nlos: int, idx, phi_pk=None, amp=None, q_pk=None, u_pk=None,
+                  stream=None):
+    import torch
+    f32 = torch.float32
+    _check("rmsynth_peaks", load_library().rmsynth_peaks(
+        plan, _dev(Fq, "Fq", f32), _dev(Fu, "Fu", f32), int(nlos), _dev(idx, "idx", torch.int32),
+        _dev(phi_pk, "phi_pk", f32), _dev(amp, "amp", f32), _dev(q_pk, "q_pk", f32),
+        _dev(u_pk, "u_pk", f32), _stream(stream)))
+
+
+def rmsynth_destroy(plan):
+    if plan:
+        load_library().rmsynth_destroy(plan)
+
+
+def rmsynth_last_error() -> str:
+    return load_library().rmsynth_last_error().decode()
+
+
+def rmsynth_version() -> str:
+    return load_library().rmsynth_version().decode()
+
+
+# ------------------------------------------------------------------ convenience
+class Plan:
+    """Owns an rmsynth plan; allocates outputs with torch on the current device."""
+
+    def __init__(self, lambda2, weights, phi, lambda0_sq: float = float("nan")):
+        self.handle = rmsynth_plan(lambda2, weights, phi, lambda0_sq)
+        self.info = rmsynth_plan_info(self.handle)
+        self.nchan, self.nphi = self.info["nchan"], self.info["nphi"]
+
+    def close(self):
+        if self.handle:
+            rmsynth_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def rmsf(self):
+        import torch
+        re = torch.empty(self.nphi, dtype=torch.float32, device="cuda")
+        im = torch.empty_like(re)
+        rmsynth_rmsf(self.handle, re, im)
+        return re, im
+
+    def execute(self, Q, U, layout: int = RMSYNTH_LOS_MAJOR, precision: int = RMSYNTH_FP32,
+                want_abs: bool = False, out: Optional[tuple] = None):
+        import torch
+        nlos = Q.shape[0] if layout == RMSYNTH_LOS_MAJOR else Q.shape[1]
+        if out is None:
+            Fq = torch.empty((nlos, self.nphi), dtype=torch.float32, device=Q.device)
+            Fu = torch.empty_like(Fq)
+            Fa = torch.empty_like(Fq) if want_abs else None
+        else:
+            Fq, Fu, Fa = out
+        ws_bytes = rmsynth_workspace_size(self.handle, nlos, layout, precision)
+        ws = torch.empty(ws_bytes, dtype=torch.uint8, device=Q.device) if ws_bytes else None
+        rmsynth_execute(self.handle, Q, U, nlos, layout, precision, Fq, Fu, Fa, ws, ws_bytes)
+        return Fq, Fu, Fa
+
+    def peaks(self, Fq, Fu):
+        import torch
+        nlos = Fq.shape[0]
+        dev = Fq.device
+        out = dict(idx=torch.empty(nlos, dtype=torch.int32, device=dev),
+                   phi_pk=torch.empty(nlos, dtype=torch.float32, device=dev),
+                   amp=torch.empty(nlos, dtype=torch.float32, device=dev),
+                   q_pk=torch.empty(nlos, dtype=torch.float32, device=dev),
+                   u_pk=torch.empty(nlos, dtype=torch.float32, device=dev))
+        rmsynth_peaks(self.handle, Fq, Fu, nlos, out["idx"], out["phi_pk"], out["amp"],
+                      out["q_pk"], out["u_pk"])
+        return out

@@ -1,0 +1,263 @@
+"""Parity of the HIP path with the FP64 oracle, through the C ABI.
+
+Bar: per-LOS error max_k |F_gpu - F_oracle| / max_k |F_oracle| <= 1e-5 for
+the FP32 and the split-bfloat16 paths; peak indices equal wherever the
+oracle's peak margin exceeds 2e-5 (elsewhere the GPU index must point at a
+value within that margin of the maximum).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1810_06250_amd as rs
+from synthetic import (WORKLOADS, band_lambda2, thin_spectrum, make_small_cube, make_cube,
+                       stratified_subsample, FREQ_MAJOR, LOS_MAJOR)
+from gpu_util import PREC_TOL, dev32, host, note
+
+pytestmark = pytest.mark.gpu
+
+PRECS = {"fp32": rs.RMSYNTH_FP32, "bf16x3": rs.RMSYNTH_SPLIT_BF16}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    rs.load_library()
+    oracle.build(force=False)
+
+
+def _run(plan, Q, U, layout, prec, want_abs=True):
+    Fq, Fu, Fa = plan.execute(Q, U, layout, prec, want_abs=want_abs)
+    pk = plan.peaks(Fq, Fu)
+    out = dict(Fq=host(Fq), Fu=host(Fu), Fa=host(Fa) if Fa is not None else None)
+    out.update({k: host(v) for k, v in pk.items()})
+    return out
+
+
+def _check(out, Q64, U64, lam, w, phi, layout, tol, margin=2e-5):
+    rq, ru = oracle.fdf(Q64, U64, lam, w, phi, layout=layout)
+    err = oracle.per_los_error(out["Fq"], out["Fu"], rq, ru)
+    assert np.all(np.isfinite(err)), "non-finite GPU output"
+    assert err.max() <= tol, f"max per-LOS error {err.max():.3e} > {tol:.1e}"
+    ref = oracle.peaks(rq, ru, phi)
+    nun, mism, bad = oracle.peak_agreement(out["idx"], rq, ru, ref, margin)
+    assert mism == 0 and bad == 0, f"peak mismatches: {mism} of {nun} unambiguous, {bad} ambiguous"
+    if out["Fa"] is not None:
+        np.testing.assert_allclose(out["Fa"], np.hypot(out["Fq"], out["Fu"]), rtol=1e-6, atol=1e-30)
+    ok = out["idx"] >= 0
+    np.testing.assert_array_equal(out["phi_pk"][ok], phi[out["idx"][ok]].astype(np.float32))
+    rows = np.arange(out["Fq"].shape[0])[ok]
+    np.testing.assert_array_equal(out["q_pk"][ok], out["Fq"][rows, out["idx"][ok]])
+    amp = np.sqrt(out["Fq"][rows, out["idx"][ok]].astype(np.float64) ** 2 +
+                  out["Fu"][rows, out["idx"][ok]].astype(np.float64) ** 2)
+    np.testing.assert_allclose(out["amp"][ok], amp, rtol=1e-6, atol=1e-30)
+    return err, rq, ru
+
+
+@pytest.mark.parametrize("prec", list(PRECS))
+def test_c1_full_cube(prec):
+    """64x64 LOS, 128 channels, 201 phi, 20 injected thin sources."""
+    wl = WORKLOADS["c1"]
+    note(f"c1 full cube, {prec}")
+    cube = make_cube(wl, device="cpu")
+    plan = rs.Plan(cube["lambda2"], cube["weights"], cube["phi"])
+    out = _run(plan, dev32(cube["Q"]), dev32(cube["U"]), LOS_MAJOR, PRECS[prec])
+    _check(out, cube["Q"].double().numpy(), cube["U"].double().numpy(), cube["lambda2"],
+           cube["weights"], cube["phi"], LOS_MAJOR, PREC_TOL[prec])
+
+
+@pytest.mark.parametrize("prec", list(PRECS))
+def test_frequency_major_equals_los_major(prec):
+    """Both input layouts feed the same arithmetic: outputs are bitwise equal."""
+    note(f"layouts bitwise, {prec}")
+    c = make_small_cube(333, 77, 150, seed=3, nflag=6, nsrc=5)
+    plan = rs.Plan(c["lambda2"], c["weights"], c["phi"])
+    a = _run(plan, dev32(c["Q"]), dev32(c["U"]), LOS_MAJOR, PRECS[prec])
+    b = _run(plan, dev32(c["Q"].T), dev32(c["U"].T), FREQ_MAJOR, PRECS[prec])
+    for k in ("Fq", "Fu", "Fa", "idx"):
+        np.testing.assert_array_equal(a[k], b[k])
+
+
+SHAPES = [(1, 1, 1), (1, 3, 5), (37, 5, 7), (64, 8, 128), (130, 13, 129), (129, 64, 257),
+          (300, 33, 300), (257, 100, 1), (2, 200, 513)]
+
+
+@pytest.mark.parametrize("prec", list(PRECS))
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s)))
+@pytest.mark.parametrize("layout", [LOS_MAJOR, FREQ_MAJOR], ids=["los", "freq"])
+def test_ragged_shapes(prec, shape, layout):
+    """Sizes that fill several tiles and leave ragged LOS, channel and phi tails."""
+    nlos, nchan, nphi = shape
+    note(f"ragged {shape} layout={layout} {prec}")
+    c = make_small_cube(nlos, nchan, nphi, seed=nlos * 7 + nchan, nflag=nchan // 10,
+                        nsrc=max(1, nlos // 20))
+    plan = rs.Plan(c["lambda2"], c["weights"], c["phi"])
+    Q, U = (c["Q"], c["U"]) if layout == LOS_MAJOR else (c["Q"].T, c["U"].T)
+    Q32, U32 = np.float32(Q), np.float32(U)
+    out = _run(plan, dev32(Q32), dev32(U32), layout, PRECS[prec])
+    _check(out, Q32.astype(np.float64), U32.astype(np.float64), c["lambda2"], c["weights"],
+           c["phi"], layout, PREC_TOL[prec])
+
+
+@pytest.mark.parametrize("prec", list(PRECS))
+def test_flagged_and_nonfinite_channels(prec):
+    """NaN/Inf in flagged channels has no effect; a NaN in an unflagged channel
+    poisons only its own LOS (idx = -1)."""
+    note(f"flags and NaN, {prec}")
+    c = make_small_cube(200, 96, 101, seed=5, nflag=12, nsrc=4)
+    plan = rs.Plan(c["lambda2"], c["weights"], c["phi"])
+    Q32, U32 = np.float32(c["Q"]), np.float32(c["U"])
+    base = _run(plan, dev32(Q32), dev32(U32), LOS_MAJOR, PRECS[prec])
+    fl = c["weights"] == 0
+    Qb, Ub = Q32.copy(), U32.copy()
+    Qb[:, fl] = np.nan
+    Ub[:, fl] = np.inf
+    out = _run(plan, dev32(Qb), dev32(Ub), LOS_MAJOR, PRECS[prec])
+    for k in ("Fq", "Fu", "idx"):
+        np.testing.assert_array_equal(out[k], base[k])
+    Qc = Q32.copy()
+    unfl = np.flatnonzero(~fl)[3]
+    Qc[17, unfl] = np.nan
+    out = _run(plan, dev32(Qc), dev32(U32), LOS_MAJOR, PRECS[prec])
+    assert out["idx"][17] == -1 and np.isnan(out["amp"][17])
+    keep = np.arange(200) != 17
+    np.testing.assert_array_equal(out["Fq"][keep], base["Fq"][keep])
+    np.testing.assert_array_equal(out["idx"][keep], base["idx"][keep])
+
+
+def test_rmsf_matches_oracle_and_unit_spectrum():
+    note("rmsf")
+    import torch
+    for name in ("c1", "c3", "c4"):
+        wl = WORKLOADS[name]
+        lam, w, phi = wl.lambda2(), wl.weights(), wl.phi()
+        plan = rs.Plan(lam, w, phi)
+        re, im = (host(x) for x in plan.rmsf())
+        rr, ri = oracle.rmsf(lam, w, phi)
+        assert np.max(np.hypot(re - rr, im - ri)) < 2e-6
+        k0 = np.flatnonzero(phi == 0.0)
+        assert abs(re[k0[0]] - 1.0) < 1e-6 and abs(im[k0[0]]) < 1e-6
+        ones = torch.ones((1, lam.size), dtype=torch.float32, device="cuda")
+        zeros = torch.zeros_like(ones)
+        Fq, Fu, _ = plan.execute(ones, zeros, LOS_MAJOR, rs.RMSYNTH_FP32)
+        np.testing.assert_allclose(host(Fq)[0], re, rtol=0, atol=2e-6)
+        np.testing.assert_allclose(host(Fu)[0], im, rtol=0, atol=2e-6)
+
+
+def test_phase_generator_accuracy():
+    """One channel, lambda0^2 = 0: R(phi) = exp(-2 i phi lambda^2) exactly, so
+    the RMSF exposes the generator's cos/sin over arguments up to ~1.5e4 rad."""
+    note("phase generator accuracy")
+    phi = np.linspace(-1000.0, 1000.0, 40001)
+    worst = 0.0
+    for lam2 in (0.0277, 0.9, 3.1, 7.43):
+        plan = rs.Plan(np.array([lam2]), np.array([1.0]), phi, lambda0_sq=0.0)
+        re, im = (host(x) for x in plan.rmsf())
+        th = 2.0 * phi * lam2
+        worst = max(worst, np.max(np.abs(re - np.cos(th))), np.max(np.abs(im + np.sin(th))))
+    assert worst < 3e-7, worst
+
+
+@pytest.mark.parametrize("prec", list(PRECS))
+def test_thin_source_peak(prec):
+    note(f"thin source peak, {prec}")
+    wl = WORKLOADS["c3"]
+    lam, w, phi = wl.lambda2(), wl.weights(), wl.phi()
+    rng = np.random.default_rng(9)
+    n = 64
+    phi0 = phi[rng.integers(100, phi.size - 100, n)]
+    P0 = rng.uniform(0.01, 0.1, n)
+    P = thin_spectrum(lam, P0, phi0, rng.uniform(0, np.pi, n))
+    plan = rs.Plan(lam, w, phi)
+    out = _run(plan, dev32(P.real), dev32(P.imag), LOS_MAJOR, PRECS[prec])
+    np.testing.assert_array_equal(out["phi_pk"], phi0.astype(np.float32))
+    np.testing.assert_allclose(out["amp"], P0, rtol=1.5e-5)
+
+
+@pytest.mark.parametrize("prec", list(PRECS))
+def test_linearity_and_determinism(prec):
+    note(f"linearity/determinism, {prec}")
+    c = make_small_cube(256, 128, 201, seed=21, nsrc=8)
+    d = make_small_cube(256, 128, 201, seed=22, nsrc=8)
+    plan = rs.Plan(c["lambda2"], c["weights"], c["phi"])
+    a, b = 0.5 - 1.25j, -0.75 + 0.5j
+    P1, P2 = c["Q"] + 1j * c["U"], d["Q"] + 1j * d["U"]
+    Pm = a * P1 + b * P2
+    r1 = _run(plan, dev32(P1.real), dev32(P1.imag), LOS_MAJOR, PRECS[prec])
+    r2 = _run(plan, dev32(P2.real), dev32(P2.imag), LOS_MAJOR, PRECS[prec])
+    rm = _run(plan, dev32(Pm.real), dev32(Pm.imag), LOS_MAJOR, PRECS[prec])
+    F1, F2 = r1["Fq"] + 1j * r1["Fu"], r2["Fq"] + 1j * r2["Fu"]
+    Fm = rm["Fq"] + 1j * rm["Fu"]
+    scale = np.abs(Fm).max(axis=1, keepdims=True)
+    assert np.max(np.abs(Fm - (a * F1 + b * F2)) / scale) < 3e-5
+    again = _run(plan, dev32(P1.real), dev32(P1.imag), LOS_MAJOR, PRECS[prec])
+    for k in ("Fq", "Fu", "idx"):
+        np.testing.assert_array_equal(again[k], r1[k])
+
+
+def test_execute_argument_errors():
+    import torch
+    c = make_small_cube(4, 16, 9, seed=1)
+    plan = rs.Plan(c["lambda2"], c["weights"], c["phi"])
+    Q = dev32(c["Q"])
+    F = torch.empty((4, 9), dtype=torch.float32, device="cuda")
+    with pytest.raises(rs.RmsynthError):
+        rs.rmsynth_execute(plan.handle, Q, Q, 4, 7, rs.RMSYNTH_FP32, F, F)
+    with pytest.raises(rs.RmsynthError):
+        rs.rmsynth_execute(plan.handle, Q, Q, 4, LOS_MAJOR, 9, F, F)
+    with pytest.raises(rs.RmsynthError):
+        rs.rmsynth_execute(plan.handle, Q, None, 4, LOS_MAJOR, rs.RMSYNTH_FP32, F, F)
+    F.fill_(7.0)
+    rs.rmsynth_execute(plan.handle, Q, Q, 0, LOS_MAJOR, rs.RMSYNTH_FP32, F, F)
+    torch.cuda.synchronize()
+    assert torch.all(F == 7.0)
+    assert rs.rmsynth_workspace_size(plan.handle, 4, LOS_MAJOR, rs.RMSYNTH_FP32) == 0
+
+
+# ------------------------------------------------------------------ full-size workloads
+def _full_size(name, prec_list, nsub):
+    import torch
+    wl = WORKLOADS[name]
+    note(f"{name} full size: generating {wl.nlos} LOS x {wl.nchan} channels")
+    cube = make_cube(wl, device="cuda")
+    plan = rs.Plan(cube["lambda2"], cube["weights"], cube["phi"])
+    sub = stratified_subsample(wl.nlos, cube["src_los"], nsub, seed=wl.seed + 11)
+    subt = torch.as_tensor(sub, device="cuda")
+    if cube["layout"] == LOS_MAJOR:
+        Qs, Us = cube["Q"][subt], cube["U"][subt]
+    else:
+        Qs, Us = cube["Q"][:, subt].t(), cube["U"][:, subt].t()
+    Q64, U64 = host(Qs).astype(np.float64), host(Us).astype(np.float64)
+    note(f"{name}: oracle on {sub.size} LOS")
+    rq, ru = oracle.fdf(Q64, U64, cube["lambda2"], cube["weights"], cube["phi"], layout=0)
+    ref = oracle.peaks(rq, ru, cube["phi"])
+    Fq = torch.empty((wl.nlos, len(cube["phi"])), dtype=torch.float32, device="cuda")
+    Fu = torch.empty_like(Fq)
+    results = {}
+    for prec in prec_list:
+        note(f"{name}: execute {prec}")
+        plan.execute(cube["Q"], cube["U"], cube["layout"], PRECS[prec], out=(Fq, Fu, None))
+        pk = plan.peaks(Fq, Fu)
+        gq, gu = host(Fq[subt]), host(Fu[subt])
+        err = oracle.per_los_error(gq, gu, rq, ru)
+        idx = host(pk["idx"])[sub]
+        nun, mism, bad = oracle.peak_agreement(idx, rq, ru, ref)
+        note(f"{name} {prec}: max per-LOS err {err.max():.3e}, peaks {mism}/{nun} mismatched, {bad} bad ambiguous")
+        results[prec] = (err.max(), mism, bad)
+        assert err.max() <= PREC_TOL[prec]
+        assert mism == 0 and bad == 0
+    del Fq, Fu, cube
+    torch.cuda.empty_cache()
+    return results
+
+
+def test_c2_full_size_sampled():
+    """512^2 LOS, 800 channels (40 flagged), 1001 phi, frequency-major."""
+    _full_size("c2", ["fp32", "bf16x3"], 2048)
+
+
+def test_c3_full_size_sampled():
+    """1024^2 LOS, 400 channels, 2001 phi, LOS-major: the benchmark workload."""
+    _full_size("c3", ["bf16x3", "fp32"], 4096)
