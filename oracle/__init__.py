@@ -15,5 +15,6 @@ from .oracle import (  # noqa: F401
     peaks,
     fdf_bruteforce,
     per_los_error,
+    incoherent_scale,
     peak_agreement,
 )

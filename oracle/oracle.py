@@ -155,12 +155,28 @@ def fdf_bruteforce(Q, U, lambda2, w, phi, lambda0_sq=None):
     return F.real.copy(), F.imag.copy()
 
 
-def per_los_error(Fq_gpu, Fu_gpu, Fq_ref, Fu_ref):
-    """e_l = max_k |F_gpu - F_ref| / max_k |F_ref| per LOS (float64)."""
+def incoherent_scale(Q, U, w, layout=0):
+    """K sqrt(sum_j w_j^2 |P_j|^2) per LOS: the typical |F| of a spectrum whose
+    channels add with random phases (finite channels of non-zero weight)."""
+    Q, U, w = _f64(Q), _f64(U), _f64(w)
+    if layout == 1:
+        Q, U = Q.T, U.T
+    keep = w > 0
+    P2 = Q[:, keep] ** 2 + U[:, keep] ** 2
+    P2 = np.where(np.isfinite(P2), P2, 0.0)
+    return np.sqrt(P2 @ (w[keep] ** 2)) / w.sum()
+
+
+def per_los_error(Fq_gpu, Fu_gpu, Fq_ref, Fu_ref, floor=None):
+    """e_l = max_k |F_gpu - F_ref| / max(max_k |F_ref|, floor_l) per LOS.
+    `floor` (e.g. `incoherent_scale`) only matters on grids so short that
+    max_k |F_ref| can fall below the LOS's typical |F|."""
     dq = np.asarray(Fq_gpu, np.float64) - Fq_ref
     du = np.asarray(Fu_gpu, np.float64) - Fu_ref
     num = np.sqrt(dq * dq + du * du).max(axis=1)
     den = np.hypot(Fq_ref, Fu_ref).max(axis=1)
+    if floor is not None:
+        den = np.maximum(den, floor)
     with np.errstate(divide="ignore", invalid="ignore"):
         return np.where(den > 0, num / den, num)
 

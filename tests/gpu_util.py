@@ -8,6 +8,16 @@ PREC_TOL = {  # per-LOS bound on max_k |F_gpu - F_oracle| / max_k |F_oracle|
     "bf16x3": 1e-5,
 }
 
+# Bound for grids too short for max_k |F| to be representative (a handful of
+# phi): the error relative to max(max_k |F|, K sqrt(sum w^2 |P|^2)).  FP32 keeps
+# 1e-5; the bfloat16 hi+lo split carries 16 significand bits per operand, so
+# one product is off by at most ~3 x 2^-16 of its size (two split residuals
+# and the dropped lo*lo term).
+SCALE_TOL = {
+    "fp32": 1e-5,
+    "bf16x3": 3 * 2.0 ** -16,
+}
+
 
 def note(msg: str):
     """Print what names the case before a GPU step, flushed."""
