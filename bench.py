@@ -38,6 +38,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32-compare", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="first run one plain device-to-device copy of this many MiB "
+                         "(a known-size reference for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -134,6 +137,16 @@ def main():
     import torch
     import paper_1810_06250_amd as rs
     from synthetic import WORKLOADS, make_cube, stratified_subsample
+
+    if args.calibrate_copy_mib > 0:
+        n = args.calibrate_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {args.calibrate_copy_mib} MiB read + written")
+        del src, dst
 
     wl = WORKLOADS[args.workload]
     log(f"generating {args.workload}: {wl.nlos} LOS x {wl.nchan} ch x {len(wl.phi())} phi")

@@ -43,10 +43,47 @@ int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 void free_plan(rmsynth_plan_s* p)
 {
     if (!p) return;
-    if (p->d_b) (void)hipFree(p->d_b);
-    if (p->d_w) (void)hipFree(p->d_w);
-    if (p->d_phi) (void)hipFree(p->d_phi);
+    void* bufs[] = {p->d_b, p->d_w, p->d_phi, p->d_base, p->d_Tbf[0], p->d_Tbf[1],
+                    p->d_Thf[0], p->d_Thf[1], p->d_Tf32};
+    for (void* b : bufs)
+        if (b) (void)hipFree(b);
     delete p;
+}
+
+// A grid is treated as uniform when every phi_k lies within 1e-9 of the
+// grid's scale from phi_0 + k dphi, dphi = (phi_last - phi_0) / (nphi - 1).
+bool detect_uniform(const double* phi, int32_t nphi, double* phi0, double* dphi)
+{
+    *phi0 = phi[0];
+    *dphi = nphi > 1 ? (phi[nphi - 1] - phi[0]) / (nphi - 1) : 0.0;
+    double scale = std::max(std::fabs(phi[0]), std::fabs(phi[nphi - 1]));
+    scale = std::max(scale, std::fabs(*dphi));
+    for (int32_t k = 0; k < nphi; ++k)
+        if (std::fabs(phi[k] - (*phi0 + k * *dphi)) > 1e-9 * std::max(scale, 1e-300)) return false;
+    return true;
+}
+
+int build_factor_tables(rmsynth_plan_s* p)
+{
+    p->ftiles = (int32_t)((p->nphi + kFactorTile - 1) / kFactorTile);
+    const size_t nT = (size_t)(p->nchan_pad / 4) * kFactorTile;
+    hipError_t e;
+    if ((e = hipMalloc(&p->d_base, sizeof(float2) * (size_t)p->ftiles * p->nchan_pad)) != hipSuccess ||
+        (e = hipMalloc(&p->d_Tbf[0], sizeof(uint4) * nT)) != hipSuccess ||
+        (e = hipMalloc(&p->d_Tbf[1], sizeof(uint4) * nT)) != hipSuccess ||
+        (e = hipMalloc(&p->d_Thf[0], sizeof(uint4) * nT)) != hipSuccess ||
+        (e = hipMalloc(&p->d_Thf[1], sizeof(uint4) * nT)) != hipSuccess ||
+        (e = hipMalloc(&p->d_Tf32, sizeof(float4) * 2 * nT)) != hipSuccess)
+        return fail(RMSYNTH_ENOMEM, "rmsynth_plan: hipMalloc (phase tables): %s", hipGetErrorString(e));
+    hipStream_t s = nullptr;
+    if ((e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) != hipSuccess)
+        return hip_fail(e, "rmsynth_plan: hipStreamCreate");
+    e = launch_factor_tables(*p, s);
+    hipError_t e2 = hipStreamSynchronize(s);
+    (void)hipStreamDestroy(s);
+    if (e != hipSuccess) return hip_fail(e, "rmsynth_plan: phase-table kernel");
+    if (e2 != hipSuccess) return hip_fail(e2, "rmsynth_plan: phase-table kernel");
+    return RMSYNTH_OK;
 }
 
 int check_device(const rmsynth_plan_s* p)
@@ -129,6 +166,13 @@ int rmsynth_plan(const double* lambda2, const double* weights, int32_t nchan, co
         free_plan(p);
         return hip_fail(e, "rmsynth_plan: hipMemcpy");
     }
+    p->uniform = detect_uniform(phi, nphi, &p->phi0, &p->dphi);
+    if (p->uniform) {
+        if (int rc = build_factor_tables(p)) {
+            free_plan(p);
+            return rc;
+        }
+    }
     *out = p;
     return ok();
 }
@@ -209,8 +253,10 @@ int rmsynth_execute(rmsynth_plan_t p, const float* Q, const float* U, int64_t nl
         a.Fu = Fu + l0 * p->nphi;
         a.Fabs = Fabs ? Fabs + l0 * p->nphi : nullptr;
         a.stream = (hipStream_t)stream;
-        hipError_t e = precision == RMSYNTH_FP32 ? launch_synth_fp32(*p, a)
-                                                 : launch_synth_split(*p, a, precision);
+        hipError_t e;
+        if (precision == RMSYNTH_FP32) e = launch_synth_fp32(*p, a);
+        else if (p->uniform) e = launch_synth_factored(*p, a, precision);
+        else e = launch_synth_split(*p, a, precision);
         if (e != hipSuccess) return hip_fail(e, "rmsynth_execute launch");
         l0 += n;
     }

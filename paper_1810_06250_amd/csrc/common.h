@@ -28,7 +28,22 @@ struct rmsynth_plan_s {
     double* d_b;
     float* d_w;
     double* d_phi;
+    // Factored phase tables, present when the phi grid is uniform
+    // (phi_k = phi_0 + k dphi).  With tiles of kFactorTile phi,
+    //   exp(-i theta_{j, k0+m}) = exp(-i theta_{j, k0}) * exp(-2i a_j m dphi):
+    //   d_base [ftiles][nchan_pad] float2  K w_j (cos, sin)(theta_{j,k0}), k0 = tile start
+    //   d_T{fmt}[hi/lo] [nchan_pad/4][kFactorTile] uint4: 4 channels x (cos, sin)
+    //                   of 2 a_j m dphi, split into 16-bit hi/lo
+    bool uniform;
+    double phi0, dphi;
+    int32_t ftiles;
+    float2* d_base;
+    uint4* d_Tbf[2];
+    uint4* d_Thf[2];
+    float4* d_Tf32;      // [nchan_pad/2][kFactorTile]: 2 channels x (cos, sin), FP32
 };
+
+constexpr int kFactorTile = 128;  // phi per tile of the factored kernels
 
 constexpr int kChanPad = 32;    // channel padding granule (largest K-step)
 constexpr int kPhiPad = 256;    // phi padding granule (largest phi tile)
@@ -102,7 +117,7 @@ __device__ __forceinline__ void split2_f16(float a, float b, uint32_t& hi, uint3
 // Flipping the sign bit of a 16-bit float is exact in both formats.
 __device__ __forceinline__ uint32_t swap_negate(uint32_t d)
 {
-    return (d >> 16) | ((d ^ 0x8000u) << 16);
+    return __builtin_amdgcn_alignbit(d, d, 16) ^ 0x80000000u;
 }
 
 // Map a hardware workgroup id to a logical tile so that logical neighbours
@@ -134,6 +149,8 @@ struct ExecArgs {
 
 hipError_t launch_synth_fp32(const rmsynth_plan_s& p, const ExecArgs& a);
 hipError_t launch_synth_split(const rmsynth_plan_s& p, const ExecArgs& a, int precision);
+hipError_t launch_synth_factored(const rmsynth_plan_s& p, const ExecArgs& a, int precision);
+hipError_t launch_factor_tables(const rmsynth_plan_s& p, hipStream_t s);
 hipError_t launch_peaks(const rmsynth_plan_s& p, const float* Fq, const float* Fu, int64_t nlos,
                         int32_t* idx, float* phi_pk, float* amp, float* q_pk, float* u_pk,
                         hipStream_t s);

@@ -1,0 +1,368 @@
+// Faraday-depth transform on a uniform phi grid with a factored phase matrix.
+//
+// For phi_k = phi_0 + k dphi and a tile of NT phi starting at k0,
+//   exp(-i theta_{j,k0+m}) = exp(-i theta_{j,k0}) * exp(-2i a_j m dphi),
+// so (eqs. (11), (13))
+//   F_l(k0 + m) = sum_j [K w_j X_lj exp(-i theta_{j,k0})] T_jm,
+//   T_jm = exp(-2i a_j m dphi).
+// The bracket is a per-channel rotation of the data, applied while the Q/U
+// tile is packed into LDS; T does not depend on the tile and is a table of
+// nchan x NT entries built once per plan (FP64 argument reduction, then split
+// into 16-bit hi/lo), small enough to stay in every XCD's L2.  The
+// nchan x nphi phase matrix itself is never formed.
+//
+// Contraction: v_mfma_f32_32x32x16_{bf16,f16}, hi*hi + hi*lo + lo*hi with FP32
+// accumulation.  Real form of eqs. (15)-(16): A rows (x', y') and (y', -x')
+// per LOS, B columns (cos, sin) of T.  In A, each 32-row MFMA block holds the
+// real-part rows of 16 LOS followed by their imaginary-part rows, so Re F and
+// Im F of a LOS land in the same lane (accumulators v and v + 8).
+//
+// Workgroup: 256 threads, 128 LOS x 128 phi, 8 channels per K-step (one MFMA
+// K of 16), LDS double buffered (2 x 24 KB).  Waves 2 x 2, each 128 rows x
+// 64 columns = 4 x 2 blocks (128 accumulators per lane), so two workgroups
+// share a CU: while one waits on memory, a barrier or its output stores, the
+// other keeps the matrix cores busy.
+#include "common.h"
+
+namespace {
+
+constexpr int MT = 128;          // LOS per tile
+constexpr int ROWS = 2 * MT;     // A rows
+constexpr int NT = kFactorTile;  // phi per tile
+constexpr int KC = 8;            // channels per K-step
+constexpr int NQ = KC / 4;       // channel quads per K-step
+
+struct ABuf {
+    uint4 a_hi[NQ][ROWS];
+    uint4 a_lo[NQ][ROWS];
+};
+struct BBuf {
+    uint4 b_hi[NQ][NT];
+    uint4 b_lo[NQ][NT];
+};
+
+typedef const __attribute__((address_space(4))) f32x4_t* const_f4_ptr;
+
+template <bool FP16>
+__device__ __forceinline__ void split2(float a, float b, uint32_t& hi, uint32_t& lo)
+{
+    if (FP16) split2_f16(a, b, hi, lo);
+    else split2_bf16(a, b, hi, lo);
+}
+
+template <bool FP16>
+__device__ __forceinline__ f32x16_t mfma16(uint4 a, uint4 b, f32x16_t c)
+{
+    if (FP16)
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8_t, a),
+                                                      __builtin_bit_cast(f16x8_t, b), c, 0, 0, 0);
+    else
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, a),
+                                                       __builtin_bit_cast(bf16x8_t, b), c, 0, 0, 0);
+}
+
+// FAST: every K-step holds KC real channels (nchan % KC == 0) and, for
+// LOS-major input, rows are 16-byte aligned; the K-loop is then branch-free.
+template <int LAYOUT, bool FP16, bool FAST>
+__global__ __launch_bounds__(256, 2) void synth_factored_kernel(
+    const float* __restrict__ Q, const float* __restrict__ U, int64_t nlos, int64_t ld,
+    int nchan, const float2* __restrict__ base, const uint4* __restrict__ Thi,
+    const uint4* __restrict__ Tlo, int nchan_pad, int nk, int nphi, int tiles_n,
+    float* __restrict__ Fq, float* __restrict__ Fu, float* __restrict__ Fabs)
+{
+    // Double-buffered A tiles (packed data) and T tiles (phase table).
+    __shared__ ABuf a0, a1;
+    __shared__ BBuf b0, b1;
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t tm = tile / tiles_n;
+    const int tn = (int)(tile - tm * tiles_n);
+    const int64_t l0 = tm * MT;
+    const int n0 = tn * NT;
+    const int t = threadIdx.x, lane = t & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int wr = wave >> 1, wc = wave & 1;
+
+    // Pack role: LOS la of the tile, channel quad hh.  hh is uniform over a
+    // wave, so the channel rotations are scalar loads.
+    const int hh = wave >> 1;
+    const int la = t & 127;
+    const int64_t lg = l0 + la;
+    // Rows past the cube read the last LOS (in bounds); their outputs are never stored.
+    const int64_t lr = lg < nlos ? lg : nlos - 1;
+    const int rre = 32 * (la >> 4) + (la & 15);  // real-part row; imaginary row is +16
+    const_f4_ptr bt = (const_f4_ptr)(base + (int64_t)tn * nchan_pad);
+
+    // Q/U and channel rotations of one K-step (4 channels of this thread),
+    // held in registers; two sets alternate so loads run two K-steps ahead.
+    struct Regs {
+        float q[4], u[4];
+        f32x4_t rot[2];  // K w_j (cos, sin) of theta_{j,k0}, 2 channels per vector
+        uint4 th, tl;    // this thread's 16-byte share of the K-step's T tile
+    };
+    Regs R0, R1;
+
+    auto gload = [&](Regs& R, int ks) {
+        const int j0 = ks * KC + 4 * hh;
+        R.th = Thi[(int64_t)ks * (NQ * NT) + t];
+        R.tl = Tlo[(int64_t)ks * (NQ * NT) + t];
+        R.rot[0] = bt[(j0 >> 1)];
+        R.rot[1] = bt[(j0 >> 1) + 1];
+        if (FAST) {
+            if (LAYOUT == RMSYNTH_LOS_MAJOR) {
+                const float4 a = *reinterpret_cast<const float4*>(Q + lr * ld + j0);
+                const float4 c = *reinterpret_cast<const float4*>(U + lr * ld + j0);
+                R.q[0] = a.x; R.q[1] = a.y; R.q[2] = a.z; R.q[3] = a.w;
+                R.u[0] = c.x; R.u[1] = c.y; R.u[2] = c.z; R.u[3] = c.w;
+            } else {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    R.q[i] = Q[(int64_t)(j0 + i) * ld + lr];
+                    R.u[i] = U[(int64_t)(j0 + i) * ld + lr];
+                }
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const bool ok = (j0 + i) < nchan;
+                const int64_t at = LAYOUT == RMSYNTH_LOS_MAJOR ? lr * ld + j0 + i
+                                                               : (int64_t)(j0 + i) * ld + lr;
+                R.q[i] = ok ? Q[at] : 0.0f;
+                R.u[i] = ok ? U[at] : 0.0f;
+            }
+        }
+    };
+
+    // Channel i of the thread's 4: rotate, split.  A channel of weight 0
+    // (rotation exactly 0) contributes 0 whatever it holds, NaN included.
+    uint32_t hi[4], lo[4];
+    auto pack1 = [&](const Regs& R, int i) {
+        const f32x4_t rr = R.rot[i >> 1];
+        const float rc = (i & 1) ? rr.z : rr.x;
+        const float rs = (i & 1) ? rr.w : rr.y;
+        const bool flagged = ((__float_as_uint(rc) | __float_as_uint(rs)) << 1) == 0u;
+        float xr = __builtin_fmaf(R.q[i], rc, R.u[i] * rs);
+        float yr = __builtin_fmaf(R.u[i], rc, -(R.q[i] * rs));
+        xr = flagged ? 0.0f : xr;
+        yr = flagged ? 0.0f : yr;
+        split2<FP16>(xr, yr, hi[i], lo[i]);
+    };
+    auto store_t = [&](BBuf& b, const Regs& R) {
+        (&b.b_hi[0][0])[t] = R.th;
+        (&b.b_lo[0][0])[t] = R.tl;
+    };
+    auto store_a = [&](ABuf& b) {
+        b.a_hi[hh][rre] = make_uint4(hi[0], hi[1], hi[2], hi[3]);
+        b.a_lo[hh][rre] = make_uint4(lo[0], lo[1], lo[2], lo[3]);
+        b.a_hi[hh][rre + 16] = make_uint4(swap_negate(hi[0]), swap_negate(hi[1]),
+                                          swap_negate(hi[2]), swap_negate(hi[3]));
+        b.a_lo[hh][rre + 16] = make_uint4(swap_negate(lo[0]), swap_negate(lo[1]),
+                                          swap_negate(lo[2]), swap_negate(lo[3]));
+    };
+
+    f32x16_t acc[4][2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
+
+    const int r = lane & 31, hsel = lane >> 5;
+    // One K-step of MFMAs (8 channels = one K of 16).  With P, the packing of
+    // the next K-step's A tile (registers P) is interleaved, one channel after
+    // each row block; the next row block's A fragments are read ahead.
+    auto mma = [&](const ABuf& cur, const BBuf& curb, const Regs* P) {
+        uint4 bh[2], bl[2];
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) {
+            bh[cb] = curb.b_hi[hsel][64 * wc + 32 * cb + r];
+            bl[cb] = curb.b_lo[hsel][64 * wc + 32 * cb + r];
+        }
+        uint4 ahn = cur.a_hi[hsel][128 * wr + r];
+        uint4 aln = cur.a_lo[hsel][128 * wr + r];
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) {
+            const uint4 ah = ahn, al = aln;
+            if (rb < 3) {
+                ahn = cur.a_hi[hsel][128 * wr + 32 * (rb + 1) + r];
+                aln = cur.a_lo[hsel][128 * wr + 32 * (rb + 1) + r];
+            }
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb) {
+                acc[rb][cb] = mfma16<FP16>(al, bh[cb], acc[rb][cb]);
+                acc[rb][cb] = mfma16<FP16>(ah, bl[cb], acc[rb][cb]);
+                acc[rb][cb] = mfma16<FP16>(ah, bh[cb], acc[rb][cb]);
+            }
+            if (P) pack1(*P, rb);
+        }
+    };
+
+    // Make the next buffers visible to all waves: this wave's LDS writes
+    // done, then the barrier.  Written out instead of __syncthreads(), whose
+    // release fence would also wait for the prefetch loads still in flight
+    // (they only fill registers).
+    auto sync_next = [&]() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); };
+
+    // Prologue: K-step 0 packed into (a0, b0), K-step 1 loading into R1.
+    gload(R0, 0);
+    gload(R1, nk > 1 ? 1 : 0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) pack1(R0, i);
+    store_a(a0);
+    store_t(b0, R0);
+    sync_next();
+
+    // Pairs of K-steps: contract ks from buffers 0 while packing ks + 1 (R1)
+    // into buffers 1 and loading ks + 2 into R0; then contract ks + 1 from
+    // buffers 1 while packing ks + 2 (R0) into buffers 0 and loading ks + 3
+    // into R1.  The loads are issued at the top of a step (the scheduling
+    // barrier keeps them there); a prefetch index past the end is clamped to
+    // the last K-step (loaded, never used).
+    int ks = 0;
+    for (; ks + 2 < nk; ks += 2) {
+        gload(R0, ks + 2);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(a0, b0, &R1);
+        store_a(a1);
+        store_t(b1, R1);
+        sync_next();
+
+        gload(R1, ks + 3 < nk ? ks + 3 : nk - 1);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(a1, b1, &R0);
+        store_a(a0);
+        store_t(b0, R0);
+        sync_next();
+    }
+    if (ks + 1 < nk) {  // two K-steps left: ks in buffers 0, ks + 1 in R1
+        mma(a0, b0, &R1);
+        store_a(a1);
+        store_t(b1, R1);
+        sync_next();
+        mma(a1, b1, nullptr);
+    } else {            // one K-step left, in buffers 0
+        mma(a0, b0, nullptr);
+    }
+
+    // Epilogue: block rb holds LOS 64 wr + 16 rb + i; Re F in v < 8, Im F in v + 8.
+    // Tiles wholly inside the output (the common case) store without checks.
+    const int half = lane >> 5, col = lane & 31;
+    const int nc = n0 + 64 * wc + col;
+    const bool full = (l0 + MT <= nlos) && (n0 + NT <= nphi);
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+            const int i = 8 * (v >> 2) + 4 * half + (v & 3);
+            const int64_t l = l0 + 64 * wr + 16 * rb + i;
+            const int64_t off = l * nphi + nc;
+            float* fq = Fq + off;
+            float* fu = Fu + off;
+            if (full) {
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb) {
+                    fq[32 * cb] = acc[rb][cb][v];
+                    fu[32 * cb] = acc[rb][cb][v + 8];
+                }
+            } else if (l < nlos) {
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb)
+                    if (nc + 32 * cb < nphi) {
+                        fq[32 * cb] = acc[rb][cb][v];
+                        fu[32 * cb] = acc[rb][cb][v + 8];
+                    }
+            }
+            if (Fabs && l < nlos) {
+                float* fa = Fabs + off;
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb)
+                    if (nc + 32 * cb < nphi) {
+                        const float a = acc[rb][cb][v], b = acc[rb][cb][v + 8];
+                        fa[32 * cb] = sqrtf(a * a + b * b);
+                    }
+            }
+        }
+}
+
+// Plan-time tables (FP64 argument reduction, FP32 sin/cos):
+//   base[t][j] = K w_j (cos, sin)(2 pi (phi_0 + 256 t dphi) b_j)   (K of eq. (13) folded in)
+//   T[j][m]    = (cos, sin)(2 pi m dphi b_j), stored per 4-channel quad and split.
+__global__ void factor_tables_kernel(const double* __restrict__ bj, const float* __restrict__ wj,
+                                     int nchan_pad, int ftiles, double phi0, double dphi, double K,
+                                     float2* __restrict__ base, uint4* __restrict__ bf_hi,
+                                     uint4* __restrict__ bf_lo, uint4* __restrict__ hf_hi,
+                                     uint4* __restrict__ hf_lo, float4* __restrict__ f32)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nT = (int64_t)(nchan_pad / 4) * NT;
+    if (idx < nT) {
+        const int quad = (int)(idx / NT), m = (int)(idx % NT);
+        uint32_t bh[4], bl[4], hh[4], hl[4];
+        float cs[4], sn[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int j = 4 * quad + i;
+            phase_cos_sin((double)m * dphi * bj[j], cs[i], sn[i]);
+            split2_bf16(cs[i], sn[i], bh[i], bl[i]);
+            split2_f16(cs[i], sn[i], hh[i], hl[i]);
+        }
+        bf_hi[idx] = make_uint4(bh[0], bh[1], bh[2], bh[3]);
+        bf_lo[idx] = make_uint4(bl[0], bl[1], bl[2], bl[3]);
+        hf_hi[idx] = make_uint4(hh[0], hh[1], hh[2], hh[3]);
+        hf_lo[idx] = make_uint4(hl[0], hl[1], hl[2], hl[3]);
+        f32[(int64_t)(2 * quad) * NT + m] = make_float4(cs[0], sn[0], cs[1], sn[1]);
+        f32[(int64_t)(2 * quad + 1) * NT + m] = make_float4(cs[2], sn[2], cs[3], sn[3]);
+    }
+    const int64_t nB = (int64_t)ftiles * nchan_pad;
+    if (idx < nB) {
+        const int tt = (int)(idx / nchan_pad), j = (int)(idx % nchan_pad);
+        float c, s;
+        phase_cos_sin((phi0 + (double)tt * NT * dphi) * bj[j], c, s);
+        const float kw = (float)(K * (double)wj[j]);
+        base[idx] = make_float2(kw * c, kw * s);
+    }
+}
+
+template <bool FP16>
+hipError_t launch_t(const rmsynth_plan_s& p, const ExecArgs& a)
+{
+    const int tiles_n = p.ftiles;
+    const int nk = (p.nchan + KC - 1) / KC;
+    const int64_t tiles_m = (a.nlos + MT - 1) / MT;
+    const int64_t blocks = tiles_m * tiles_n;
+    if (blocks <= 0) return hipSuccess;
+    const uint4* Thi = FP16 ? p.d_Thf[0] : p.d_Tbf[0];
+    const uint4* Tlo = FP16 ? p.d_Thf[1] : p.d_Tbf[1];
+    const bool full_k = p.nchan % KC == 0;
+#define RMS_LAUNCH(L, F)                                                                       \
+    hipLaunchKernelGGL((synth_factored_kernel<L, FP16, F>), dim3((unsigned)blocks), dim3(256), 0, \
+                       a.stream, a.Q, a.U, a.nlos, a.ld, p.nchan, p.d_base, Thi, Tlo,            \
+                       p.nchan_pad, nk, p.nphi, tiles_n, a.Fq, a.Fu, a.Fabs)
+    if (a.layout == RMSYNTH_LOS_MAJOR) {
+        if (full_k && a.vec4) RMS_LAUNCH(RMSYNTH_LOS_MAJOR, true);
+        else RMS_LAUNCH(RMSYNTH_LOS_MAJOR, false);
+    } else {
+        if (full_k) RMS_LAUNCH(RMSYNTH_FREQ_MAJOR, true);
+        else RMS_LAUNCH(RMSYNTH_FREQ_MAJOR, false);
+    }
+#undef RMS_LAUNCH
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_synth_factored(const rmsynth_plan_s& p, const ExecArgs& a, int precision)
+{
+    return precision == RMSYNTH_SPLIT_FP16 ? launch_t<true>(p, a) : launch_t<false>(p, a);
+}
+
+hipError_t launch_factor_tables(const rmsynth_plan_s& p, hipStream_t stream)
+{
+    const int64_t nT = (int64_t)(p.nchan_pad / 4) * NT;
+    const int64_t nB = (int64_t)p.ftiles * p.nchan_pad;
+    const int64_t n = nT > nB ? nT : nB;
+    hipLaunchKernelGGL(factor_tables_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream,
+                       p.d_b, p.d_w, p.nchan_pad, p.ftiles, p.phi0, p.dphi, p.K, p.d_base, p.d_Tbf[0],
+                       p.d_Tbf[1], p.d_Thf[0], p.d_Thf[1], p.d_Tf32);
+    return hipGetLastError();
+}

@@ -263,3 +263,20 @@ def test_c2_full_size_sampled():
 def test_c3_full_size_sampled():
     """1024^2 LOS, 400 channels, 2001 phi, LOS-major: the benchmark workload."""
     _full_size("c3", ["bf16x3", "fp32"], 4096)
+
+
+@pytest.mark.parametrize("prec", list(PRECS))
+@pytest.mark.parametrize("layout", [LOS_MAJOR, FREQ_MAJOR], ids=["los", "freq"])
+def test_nonuniform_phi_grid(prec, layout):
+    """An irregular phi grid takes the per-element phase generator instead of
+    the factored tables; both must agree with the oracle."""
+    note(f"non-uniform phi grid, layout={layout} {prec}")
+    rng = np.random.default_rng(77)
+    c = make_small_cube(300, 120, 10, seed=78, nflag=7, nsrc=6)
+    phi = np.sort(rng.uniform(-150, 150, 333))
+    plan = rs.Plan(c["lambda2"], c["weights"], phi)
+    Q, U = (c["Q"], c["U"]) if layout == LOS_MAJOR else (c["Q"].T, c["U"].T)
+    Q32, U32 = np.float32(Q), np.float32(U)
+    out = _run(plan, dev32(Q32), dev32(U32), layout, PRECS[prec])
+    _check(out, Q32.astype(np.float64), U32.astype(np.float64), c["lambda2"], c["weights"],
+           phi, layout, PREC_TOL[prec])
