@@ -1,0 +1,141 @@
+/*
+ * rmsynth_mlp.h -- learned gate for RM synthesis on AMD Instinct MI355X
+ * (gfx950).
+ *
+ * The paper evaluates the Faraday dispersion function of eq. (15) for every
+ * line of sight (Sect. 3, "for all LOS").  When most lines of sight hold no
+ * polarised source, a small network that looks at the Q/U spectrum can pick
+ * the lines of sight worth the fine-grid synthesis; the others report the
+ * network's estimate.  The network is not part of the paper: this header is
+ * the boundary of that extension.  Every line of sight the gate passes is
+ * synthesised by rmsynth_execute and searched by rmsynth_peaks, exactly as in
+ * the ungated path.
+ *
+ * Network (per line of sight, nchan channels, weights w_j of the plan):
+ *   x  = [w Q | w U] / rms(w Q, w U)              (2 nchan inputs)
+ *   h1 = relu(W1 x + b1),  h2 = relu(W2 h1 + b2),  o = W3 h2 + b3
+ *   phi_hat = o[0] * phi_scale,  score = sigmoid(o[1])
+ *   loss = mean over the batch of BCE(score, det) + det (o[0] - phi/phi_scale)^2
+ * x, h1, h2, dz and the weights are rounded to IEEE half for the FP16 matrix
+ * cores (FP32 accumulation); master weights and Adam moments are FP32.
+ *
+ * Canonical parameter vector (FP32, nparams = h1 (2 nchan + 1) + h2 (h1 + 1)
+ * + 2 (h2 + 1)):  W1 [h1][2 nchan] row-major, b1 [h1], W2 [h2][h1], b2 [h2],
+ * W3 [2][h2], b3 [2].
+ *
+ * Conventions as in rmsynth.h: Q/U and all outputs are device pointers in
+ * LOS-major layout (Q[l][j]); calls are asynchronous on `stream` (a
+ * hipStream_t, NULL = default stream) unless stated otherwise; argument
+ * errors return synchronously with a message in rmsynth_last_error().  A
+ * network object keeps its own activation buffers, so one object must not be
+ * used from two streams at once.  The object lives on the device that was
+ * current at creation; calls from another device return RMSYNTH_EINVAL.
+ */
+#ifndef RMSYNTH_MLP_H
+#define RMSYNTH_MLP_H
+
+#include "rmsynth.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rmsynth_mlp_s* rmsynth_mlp_t;
+
+/*
+ * rmsynth_mlp_create -- network for spectra of `nchan` channels with hidden
+ * widths h1, h2 (multiples of 64, at most 4096).  `weights` (host, [nchan],
+ * NULL = all ones; finite, >= 0) are the channel weights applied to the
+ * inputs; zero-weight channels are ignored, as in the synthesis.
+ * phi_scale > 0 scales the Faraday-depth output.  Weights are He-normal
+ * from `seed`, biases zero, Adam moments zero.  Allocates device memory.
+ */
+int rmsynth_mlp_create(int32_t nchan, int32_t h1, int32_t h2, const float* weights,
+                       float phi_scale, uint64_t seed, rmsynth_mlp_t* out);
+
+/* rmsynth_mlp_num_params -- length of the canonical parameter vector. */
+int rmsynth_mlp_num_params(rmsynth_mlp_t mlp, int64_t* nparams);
+
+/*
+ * rmsynth_mlp_get_params / rmsynth_mlp_set_params -- copy the FP32 master
+ * parameters to / from a HOST array of nparams floats in canonical order.
+ * Synchronous (waits for the device).  set_params leaves the Adam moments
+ * and step count unchanged and refreshes the half copies.
+ */
+int rmsynth_mlp_get_params(rmsynth_mlp_t mlp, float* params);
+int rmsynth_mlp_set_params(rmsynth_mlp_t mlp, const float* params);
+
+/*
+ * rmsynth_mlp_grad -- loss and gradient of the mean loss over `batch` lines
+ * of sight, without updating the parameters.
+ *   Q, U       device [batch][nchan]
+ *   phi_label  device [batch]  Faraday depth of the brightest component
+ *   det_label  device [batch]  1 for a detection, 0 otherwise (values in [0, 1])
+ *   grad       device [nparams], canonical order (output)
+ *   loss       device [1] mean loss (output, may be NULL)
+ * batch >= 1.  Grows the object's activation buffers when needed.
+ */
+int rmsynth_mlp_grad(rmsynth_mlp_t mlp, const float* Q, const float* U, int64_t batch,
+                     const float* phi_label, const float* det_label, float* grad, float* loss,
+                     void* stream);
+
+/*
+ * rmsynth_mlp_train_step -- one Adam step (beta1 0.9, beta2 0.999, eps 1e-8,
+ * bias-corrected, learning rate lr > 0) on the gradient rmsynth_mlp_grad
+ * computes; arguments as there.
+ */
+int rmsynth_mlp_train_step(rmsynth_mlp_t mlp, const float* Q, const float* U, int64_t batch,
+                           const float* phi_label, const float* det_label, float lr, float* loss,
+                           void* stream);
+
+/*
+ * rmsynth_mlp_infer -- phi_hat and detection score for nlos >= 0 lines of
+ * sight (device [nlos] each).  A non-finite unflagged input gives NaN
+ * outputs.  Works in chunks through the object's buffers.
+ */
+int rmsynth_mlp_infer(rmsynth_mlp_t mlp, const float* Q, const float* U, int64_t nlos,
+                      float* phi_hat, float* score, void* stream);
+
+/*
+ * rmsynth_gate_workspace_size -- device workspace rmsynth_gate_execute needs
+ * for `nlos` lines of sight with this plan.
+ */
+int rmsynth_gate_workspace_size(rmsynth_plan_t plan, rmsynth_mlp_t mlp, int64_t nlos,
+                                size_t* bytes);
+
+/*
+ * rmsynth_gate_execute -- gated peak search.  For every line of sight the
+ * network gives (phi_hat, score); the line of sight is GATED when
+ * score >= tau, when either output is not finite, or when |phi_hat| lies
+ * within one RMSF width (plan's 2 sqrt(3) / span of lambda^2) of the largest
+ * |phi| of the plan's grid.  Gated lines of sight are gathered, synthesised
+ * with rmsynth_execute (FP32 path) and searched with rmsynth_peaks; the
+ * results are scattered back:
+ *   idx[l], phi_pk[l], amp[l]: the peak of eq. (15) on the plan's grid
+ *       (as rmsynth_peaks), for gated l;  idx = -1, phi_pk = phi_hat,
+ *       amp = NaN for the others.
+ *   gated[l]: 1 or 0.
+ * The plan's nchan must equal the network's.  workspace: device memory of at
+ * least rmsynth_gate_workspace_size() bytes.  Synchronises `stream` once
+ * (to read the number of gated lines of sight).
+ */
+int rmsynth_gate_execute(rmsynth_plan_t plan, rmsynth_mlp_t mlp, const float* Q, const float* U,
+                         int64_t nlos, float tau, int32_t* idx, float* phi_pk, float* amp,
+                         int32_t* gated, void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * rmsynth_mlp_save / rmsynth_mlp_load -- binary file with the shape, channel
+ * weights, phi_scale, master parameters, Adam moments and step count.  load
+ * creates a new object on the current device.  Synchronous.
+ */
+int rmsynth_mlp_save(rmsynth_mlp_t mlp, const char* path);
+int rmsynth_mlp_load(const char* path, rmsynth_mlp_t* out);
+
+/* rmsynth_mlp_destroy -- frees the object (NULL is ignored). */
+void rmsynth_mlp_destroy(rmsynth_mlp_t mlp);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RMSYNTH_MLP_H */

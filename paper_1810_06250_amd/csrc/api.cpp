@@ -12,11 +12,9 @@
 
 #include "common.h"
 
-namespace {
-
 thread_local std::string g_last_error;
 
-int fail(int code, const char* fmt, ...)
+int rms_fail(int code, const char* fmt, ...)
 {
     char buf[512];
     va_list ap;
@@ -27,18 +25,19 @@ int fail(int code, const char* fmt, ...)
     return code;
 }
 
-int ok()
+int rms_ok()
 {
     g_last_error.clear();
     return RMSYNTH_OK;
 }
 
-int hip_fail(hipError_t e, const char* what)
+int rms_hip_fail(hipError_t e, const char* what)
 {
-    return fail(RMSYNTH_EHIP, "%s: %s", what, hipGetErrorString(e));
+    return rms_fail(RMSYNTH_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
 
-int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+namespace {
+
 
 void free_plan(rmsynth_plan_s* p)
 {
@@ -74,15 +73,15 @@ int build_factor_tables(rmsynth_plan_s* p)
         (e = hipMalloc(&p->d_Thf[0], sizeof(uint4) * nT)) != hipSuccess ||
         (e = hipMalloc(&p->d_Thf[1], sizeof(uint4) * nT)) != hipSuccess ||
         (e = hipMalloc(&p->d_Tf32, sizeof(float4) * 2 * nT)) != hipSuccess)
-        return fail(RMSYNTH_ENOMEM, "rmsynth_plan: hipMalloc (phase tables): %s", hipGetErrorString(e));
+        return rms_fail(RMSYNTH_ENOMEM, "rmsynth_plan: hipMalloc (phase tables): %s", hipGetErrorString(e));
     hipStream_t s = nullptr;
     if ((e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) != hipSuccess)
-        return hip_fail(e, "rmsynth_plan: hipStreamCreate");
+        return rms_hip_fail(e, "rmsynth_plan: hipStreamCreate");
     e = launch_factor_tables(*p, s);
     hipError_t e2 = hipStreamSynchronize(s);
     (void)hipStreamDestroy(s);
-    if (e != hipSuccess) return hip_fail(e, "rmsynth_plan: phase-table kernel");
-    if (e2 != hipSuccess) return hip_fail(e2, "rmsynth_plan: phase-table kernel");
+    if (e != hipSuccess) return rms_hip_fail(e, "rmsynth_plan: phase-table kernel");
+    if (e2 != hipSuccess) return rms_hip_fail(e2, "rmsynth_plan: phase-table kernel");
     return RMSYNTH_OK;
 }
 
@@ -90,9 +89,9 @@ int check_device(const rmsynth_plan_s* p)
 {
     int dev = -1;
     hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (e != hipSuccess) return rms_hip_fail(e, "hipGetDevice");
     if (dev != p->device)
-        return fail(RMSYNTH_EINVAL, "plan was created on device %d but device %d is current",
+        return rms_fail(RMSYNTH_EINVAL, "plan was created on device %d but device %d is current",
                     p->device, dev);
     return RMSYNTH_OK;
 }
@@ -108,31 +107,31 @@ const char* rmsynth_version(void) { return "rmsynth-gfx950 0.1"; }
 int rmsynth_plan(const double* lambda2, const double* weights, int32_t nchan, const double* phi,
                  int32_t nphi, double lambda0_sq, rmsynth_plan_t* out)
 {
-    if (!out) return fail(RMSYNTH_EINVAL, "rmsynth_plan: out is NULL");
+    if (!out) return rms_fail(RMSYNTH_EINVAL, "rmsynth_plan: out is NULL");
     *out = nullptr;
-    if (!lambda2 || !weights || !phi) return fail(RMSYNTH_EINVAL, "rmsynth_plan: NULL array");
-    if (nchan < 1 || nchan > 65536) return fail(RMSYNTH_EINVAL, "rmsynth_plan: nchan=%d", nchan);
-    if (nphi < 1 || nphi > (1 << 20)) return fail(RMSYNTH_EINVAL, "rmsynth_plan: nphi=%d", nphi);
+    if (!lambda2 || !weights || !phi) return rms_fail(RMSYNTH_EINVAL, "rmsynth_plan: NULL array");
+    if (nchan < 1 || nchan > 65536) return rms_fail(RMSYNTH_EINVAL, "rmsynth_plan: nchan=%d", nchan);
+    if (nphi < 1 || nphi > (1 << 20)) return rms_fail(RMSYNTH_EINVAL, "rmsynth_plan: nphi=%d", nphi);
     double sw = 0.0, swl = 0.0, lo = INFINITY, hi = -INFINITY;
     for (int32_t j = 0; j < nchan; ++j) {
         const double w = weights[j], l = lambda2[j];
         if (!std::isfinite(w) || w < 0.0)
-            return fail(RMSYNTH_EINVAL, "rmsynth_plan: weight %d is %g", j, w);
-        if (!std::isfinite(l)) return fail(RMSYNTH_EINVAL, "rmsynth_plan: lambda2 %d is %g", j, l);
+            return rms_fail(RMSYNTH_EINVAL, "rmsynth_plan: weight %d is %g", j, w);
+        if (!std::isfinite(l)) return rms_fail(RMSYNTH_EINVAL, "rmsynth_plan: lambda2 %d is %g", j, l);
         sw += w;
         swl += w * l;
         if (w > 0.0) { lo = std::min(lo, l); hi = std::max(hi, l); }
     }
-    if (!(sw > 0.0)) return fail(RMSYNTH_EINVAL, "rmsynth_plan: sum of weights is %g", sw);
+    if (!(sw > 0.0)) return rms_fail(RMSYNTH_EINVAL, "rmsynth_plan: sum of weights is %g", sw);
     for (int32_t k = 0; k < nphi; ++k)
-        if (!std::isfinite(phi[k])) return fail(RMSYNTH_EINVAL, "rmsynth_plan: phi %d is %g", k, phi[k]);
+        if (!std::isfinite(phi[k])) return rms_fail(RMSYNTH_EINVAL, "rmsynth_plan: phi %d is %g", k, phi[k]);
     if (!std::isnan(lambda0_sq) && !std::isfinite(lambda0_sq))
-        return fail(RMSYNTH_EINVAL, "rmsynth_plan: lambda0_sq is %g", lambda0_sq);
+        return rms_fail(RMSYNTH_EINVAL, "rmsynth_plan: lambda0_sq is %g", lambda0_sq);
 
     auto* p = new (std::nothrow) rmsynth_plan_s{};
-    if (!p) return fail(RMSYNTH_ENOMEM, "rmsynth_plan: host allocation");
+    if (!p) return rms_fail(RMSYNTH_ENOMEM, "rmsynth_plan: host allocation");
     hipError_t e = hipGetDevice(&p->device);
-    if (e != hipSuccess) { free_plan(p); return hip_fail(e, "hipGetDevice"); }
+    if (e != hipSuccess) { free_plan(p); return rms_hip_fail(e, "hipGetDevice"); }
     p->nchan = nchan;
     p->nphi = nphi;
     p->nchan_pad = (int32_t)round_up(nchan, kChanPad);
@@ -153,18 +152,19 @@ int rmsynth_plan(const double* lambda2, const double* weights, int32_t nchan, co
         hw[j] = (float)weights[j];
     }
     std::copy(phi, phi + nphi, hphi.begin());
+    for (int32_t k = 0; k < nphi; ++k) p->phi_absmax = std::max(p->phi_absmax, std::fabs(phi[k]));
 
     if ((e = hipMalloc(&p->d_b, sizeof(double) * p->nchan_pad)) != hipSuccess ||
         (e = hipMalloc(&p->d_w, sizeof(float) * p->nchan_pad)) != hipSuccess ||
         (e = hipMalloc(&p->d_phi, sizeof(double) * p->nphi_pad)) != hipSuccess) {
         free_plan(p);
-        return fail(RMSYNTH_ENOMEM, "rmsynth_plan: hipMalloc: %s", hipGetErrorString(e));
+        return rms_fail(RMSYNTH_ENOMEM, "rmsynth_plan: hipMalloc: %s", hipGetErrorString(e));
     }
     if ((e = hipMemcpy(p->d_b, hb.data(), sizeof(double) * p->nchan_pad, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(p->d_w, hw.data(), sizeof(float) * p->nchan_pad, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(p->d_phi, hphi.data(), sizeof(double) * p->nphi_pad, hipMemcpyHostToDevice)) != hipSuccess) {
         free_plan(p);
-        return hip_fail(e, "rmsynth_plan: hipMemcpy");
+        return rms_hip_fail(e, "rmsynth_plan: hipMemcpy");
     }
     p->uniform = detect_uniform(phi, nphi, &p->phi0, &p->dphi);
     if (p->uniform) {
@@ -174,60 +174,65 @@ int rmsynth_plan(const double* lambda2, const double* weights, int32_t nchan, co
         }
     }
     *out = p;
-    return ok();
+    return rms_ok();
 }
 
 int rmsynth_plan_info(rmsynth_plan_t p, double* K, double* lambda0_sq, double* fwhm_est,
                       double* phimax_est, int32_t* nchan, int32_t* nphi)
 {
-    if (!p) return fail(RMSYNTH_EINVAL, "rmsynth_plan_info: plan is NULL");
+    if (!p) return rms_fail(RMSYNTH_EINVAL, "rmsynth_plan_info: plan is NULL");
     if (K) *K = p->K;
     if (lambda0_sq) *lambda0_sq = p->lambda0_sq;
     if (fwhm_est) *fwhm_est = p->fwhm_est;
     if (phimax_est) *phimax_est = p->phimax_est;
     if (nchan) *nchan = p->nchan;
     if (nphi) *nphi = p->nphi;
-    return ok();
+    return rms_ok();
 }
 
 int rmsynth_workspace_size(rmsynth_plan_t p, int64_t nlos, int32_t layout, int32_t precision,
                            size_t* bytes)
 {
-    if (!p || !bytes) return fail(RMSYNTH_EINVAL, "rmsynth_workspace_size: NULL argument");
-    if (nlos < 0) return fail(RMSYNTH_EINVAL, "rmsynth_workspace_size: nlos=%lld", (long long)nlos);
+    if (!p || !bytes) return rms_fail(RMSYNTH_EINVAL, "rmsynth_workspace_size: NULL argument");
+    if (nlos < 0) return rms_fail(RMSYNTH_EINVAL, "rmsynth_workspace_size: nlos=%lld", (long long)nlos);
     if (layout != RMSYNTH_LOS_MAJOR && layout != RMSYNTH_FREQ_MAJOR)
-        return fail(RMSYNTH_EINVAL, "rmsynth_workspace_size: layout=%d", layout);
+        return rms_fail(RMSYNTH_EINVAL, "rmsynth_workspace_size: layout=%d", layout);
     if (precision < RMSYNTH_FP32 || precision > RMSYNTH_SPLIT_FP16)
-        return fail(RMSYNTH_EINVAL, "rmsynth_workspace_size: precision=%d", precision);
-    *bytes = 0;
-    return ok();
+        return rms_fail(RMSYNTH_EINVAL, "rmsynth_workspace_size: precision=%d", precision);
+    *bytes = precision == RMSYNTH_SPLIT_FP16 ? (size_t)round_up(std::max<int64_t>(nlos, 1) * 4, 256) : 0;
+    return rms_ok();
 }
 
 int rmsynth_rmsf(rmsynth_plan_t p, float* R_re, float* R_im, void* stream)
 {
-    if (!p || !R_re || !R_im) return fail(RMSYNTH_EINVAL, "rmsynth_rmsf: NULL argument");
+    if (!p || !R_re || !R_im) return rms_fail(RMSYNTH_EINVAL, "rmsynth_rmsf: NULL argument");
     if (int rc = check_device(p)) return rc;
     hipError_t e = launch_rmsf(*p, R_re, R_im, (hipStream_t)stream);
-    if (e != hipSuccess) return hip_fail(e, "rmsynth_rmsf launch");
-    return ok();
+    if (e != hipSuccess) return rms_hip_fail(e, "rmsynth_rmsf launch");
+    return rms_ok();
 }
 
 int rmsynth_execute(rmsynth_plan_t p, const float* Q, const float* U, int64_t nlos, int32_t layout,
                     int32_t precision, float* Fq, float* Fu, float* Fabs, void* workspace,
                     size_t workspace_bytes, void* stream)
 {
-    (void)workspace;
-    (void)workspace_bytes;
-    if (!p) return fail(RMSYNTH_EINVAL, "rmsynth_execute: plan is NULL");
-    if (nlos < 0) return fail(RMSYNTH_EINVAL, "rmsynth_execute: nlos=%lld", (long long)nlos);
+    if (!p) return rms_fail(RMSYNTH_EINVAL, "rmsynth_execute: plan is NULL");
+    if (nlos < 0) return rms_fail(RMSYNTH_EINVAL, "rmsynth_execute: nlos=%lld", (long long)nlos);
     if (layout != RMSYNTH_LOS_MAJOR && layout != RMSYNTH_FREQ_MAJOR)
-        return fail(RMSYNTH_EINVAL, "rmsynth_execute: layout=%d", layout);
+        return rms_fail(RMSYNTH_EINVAL, "rmsynth_execute: layout=%d", layout);
     if (precision < RMSYNTH_FP32 || precision > RMSYNTH_SPLIT_FP16)
-        return fail(RMSYNTH_EINVAL, "rmsynth_execute: precision=%d", precision);
-    if (nlos == 0) return ok();
-    if (!Q || !U || !Fq || !Fu) return fail(RMSYNTH_EINVAL, "rmsynth_execute: NULL buffer");
-    if (precision == RMSYNTH_SPLIT_FP16)
-        return fail(RMSYNTH_EUNSUPPORTED, "rmsynth_execute: FP16 split is not available yet");
+        return rms_fail(RMSYNTH_EINVAL, "rmsynth_execute: precision=%d", precision);
+    if (nlos == 0) return rms_ok();
+    if (!Q || !U || !Fq || !Fu) return rms_fail(RMSYNTH_EINVAL, "rmsynth_execute: NULL buffer");
+    if (precision == RMSYNTH_SPLIT_FP16) {
+        if (!p->uniform)
+            return rms_fail(RMSYNTH_EUNSUPPORTED,
+                        "rmsynth_execute: the FP16 split needs a uniform phi grid");
+        const size_t need = (size_t)round_up(nlos * 4, 256);
+        if (!workspace || workspace_bytes < need)
+            return rms_fail(RMSYNTH_EWORKSPACE, "rmsynth_execute: FP16 split needs %zu workspace bytes, got %zu",
+                        need, workspace ? workspace_bytes : (size_t)0);
+    }
     if (int rc = check_device(p)) return rc;
 
     // Launch in LOS batches so that one grid stays below kMaxBlocks.
@@ -252,28 +257,33 @@ int rmsynth_execute(rmsynth_plan_t p, const float* Q, const float* U, int64_t nl
         a.Fq = Fq + l0 * p->nphi;
         a.Fu = Fu + l0 * p->nphi;
         a.Fabs = Fabs ? Fabs + l0 * p->nphi : nullptr;
+        a.los_scale = precision == RMSYNTH_SPLIT_FP16 ? static_cast<float*>(workspace) + l0 : nullptr;
         a.stream = (hipStream_t)stream;
+        if (precision == RMSYNTH_SPLIT_FP16) {
+            hipError_t e = launch_los_scale(*p, a);
+            if (e != hipSuccess) return rms_hip_fail(e, "rmsynth_execute scale launch");
+        }
         hipError_t e;
         if (precision == RMSYNTH_FP32) e = launch_synth_fp32(*p, a);
         else if (p->uniform) e = launch_synth_factored(*p, a, precision);
         else e = launch_synth_split(*p, a, precision);
-        if (e != hipSuccess) return hip_fail(e, "rmsynth_execute launch");
+        if (e != hipSuccess) return rms_hip_fail(e, "rmsynth_execute launch");
         l0 += n;
     }
-    return ok();
+    return rms_ok();
 }
 
 int rmsynth_peaks(rmsynth_plan_t p, const float* Fq, const float* Fu, int64_t nlos, int32_t* idx,
                   float* phi_pk, float* amp, float* q_pk, float* u_pk, void* stream)
 {
-    if (!p) return fail(RMSYNTH_EINVAL, "rmsynth_peaks: plan is NULL");
-    if (nlos < 0) return fail(RMSYNTH_EINVAL, "rmsynth_peaks: nlos=%lld", (long long)nlos);
-    if (nlos == 0) return ok();
-    if (!Fq || !Fu || !idx) return fail(RMSYNTH_EINVAL, "rmsynth_peaks: NULL buffer");
+    if (!p) return rms_fail(RMSYNTH_EINVAL, "rmsynth_peaks: plan is NULL");
+    if (nlos < 0) return rms_fail(RMSYNTH_EINVAL, "rmsynth_peaks: nlos=%lld", (long long)nlos);
+    if (nlos == 0) return rms_ok();
+    if (!Fq || !Fu || !idx) return rms_fail(RMSYNTH_EINVAL, "rmsynth_peaks: NULL buffer");
     if (int rc = check_device(p)) return rc;
     hipError_t e = launch_peaks(*p, Fq, Fu, nlos, idx, phi_pk, amp, q_pk, u_pk, (hipStream_t)stream);
-    if (e != hipSuccess) return hip_fail(e, "rmsynth_peaks launch");
-    return ok();
+    if (e != hipSuccess) return rms_hip_fail(e, "rmsynth_peaks launch");
+    return rms_ok();
 }
 
 void rmsynth_destroy(rmsynth_plan_t p) { free_plan(p); }

@@ -25,6 +25,7 @@ struct rmsynth_plan_s {
     int device;
     int32_t nchan, nphi, nchan_pad, nphi_pad;
     double K, lambda0_sq, fwhm_est, phimax_est;
+    double phi_absmax;   // largest |phi_k| of the grid
     double* d_b;
     float* d_w;
     double* d_phi;
@@ -144,12 +145,14 @@ struct ExecArgs {
     float* Fq;
     float* Fu;
     float* Fabs;
+    float* los_scale;  // FP16 split: per-LOS scale [nlos] in the workspace
     hipStream_t stream;
 };
 
 hipError_t launch_synth_fp32(const rmsynth_plan_s& p, const ExecArgs& a);
 hipError_t launch_synth_split(const rmsynth_plan_s& p, const ExecArgs& a, int precision);
 hipError_t launch_synth_factored(const rmsynth_plan_s& p, const ExecArgs& a, int precision);
+hipError_t launch_los_scale(const rmsynth_plan_s& p, const ExecArgs& a);
 hipError_t launch_factor_tables(const rmsynth_plan_s& p, hipStream_t s);
 hipError_t launch_peaks(const rmsynth_plan_s& p, const float* Fq, const float* Fu, int64_t nlos,
                         int32_t* idx, float* phi_pk, float* amp, float* q_pk, float* u_pk,
@@ -159,3 +162,11 @@ hipError_t launch_rmsf(const rmsynth_plan_s& p, float* re, float* im, hipStream_
 // Largest number of workgroups one launch may use (grid x dimension limit,
 // kept well inside 2^31 - 1).
 constexpr int64_t kMaxBlocks = int64_t(1) << 30;
+
+inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+// Error state shared by every entry point: set the thread's last-error text
+// and return `code`; rms_ok clears it and returns RMSYNTH_OK.
+int rms_fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int rms_ok();
+int rms_hip_fail(hipError_t e, const char* what);

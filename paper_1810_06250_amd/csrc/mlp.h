@@ -1,0 +1,37 @@
+// Launchers of the surrogate-network and gating kernels (mlp.hip, gate.hip).
+#pragma once
+#include "common.h"
+
+hipError_t mlp_launch_input(const float* Q, const float* U, int64_t nvalid, int64_t nrows, int nchan,
+                            const float* w, _Float16* X, int ldx, hipStream_t s);
+hipError_t mlp_launch_gemm(bool atr, bool btr, const _Float16* A, int64_t lda, const _Float16* B,
+                           int64_t ldb, int64_t M, int64_t N, int64_t K, float alpha,
+                           const float* bias, bool relu, const float* mask, int64_t ldm, float* C32,
+                           int64_t ldc, _Float16* C16, int64_t ldc16, hipStream_t s);
+hipError_t mlp_launch_head(const _Float16* H2, const float* Z2, int h2, const _Float16* W3,
+                           const float* b3, int64_t nvalid, int64_t nrows, float phi_scale,
+                           const float* phi_label, const float* det_label, float* loss_b,
+                           float* g_out, float* dz2, _Float16* dz2_16, float* phi_hat, float* score,
+                           hipStream_t s);
+hipError_t mlp_launch_head_wgrad(const float* g, const _Float16* H2, int h2, int64_t nb, float alpha,
+                                 float* gW3, float* gb3, hipStream_t s);
+hipError_t mlp_launch_colsum(const float* X, int64_t M, int64_t N, float alpha, float* out,
+                             hipStream_t s);
+hipError_t mlp_launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr,
+                           float beta1, float beta2, float eps, float bc1, float bc2, hipStream_t s);
+hipError_t mlp_launch_weights16(const float* p, int64_t nW1, int64_t nb1, int64_t nW2, int64_t nb2,
+                                int64_t nW3, _Float16* w16, hipStream_t s);
+hipError_t mlp_launch_mean(const float* x, int64_t n, float* out, hipStream_t s);
+
+// Gate (gate.hip).  Compaction works on blocks of 1024 lines of sight:
+// counts needs gate_num_blocks(nlos) + 1 entries and ends holding the
+// exclusive offsets and, at [nblocks], the number of gated lines of sight.
+int64_t gate_num_blocks(int64_t nlos);
+hipError_t gate_launch_compact(const float* phi_hat, const float* score, int64_t nlos, float tau,
+                               float edge, int32_t* gated, int32_t* idx, float* amp,
+                               int32_t* counts, int64_t* list, hipStream_t s);
+hipError_t gate_launch_gather(const float* Q, const float* U, const int64_t* list, int64_t n,
+                              int nchan, float* gQ, float* gU, hipStream_t s);
+hipError_t gate_launch_scatter(const int64_t* list, int64_t n, const int32_t* gidx,
+                               const float* gphi, const float* gamp, int32_t* idx, float* phi_pk,
+                               float* amp, hipStream_t s);

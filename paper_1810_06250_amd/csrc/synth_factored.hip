@@ -68,7 +68,8 @@ __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
     const float* __restrict__ Q, const float* __restrict__ U, int64_t nlos, int64_t ld,
     int nchan, const float2* __restrict__ base, const uint4* __restrict__ Thi,
     const uint4* __restrict__ Tlo, int nchan_pad, int nk, int nphi, int tiles_n,
-    float* __restrict__ Fq, float* __restrict__ Fu, float* __restrict__ Fabs)
+    float* __restrict__ Fq, float* __restrict__ Fu, float* __restrict__ Fabs,
+    const float* __restrict__ los_scale)
 {
     // Double-buffered A tiles (packed data) and T tiles (phase table).
     __shared__ ABuf a0, a1;
@@ -90,6 +91,9 @@ __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
     // Rows past the cube read the last LOS (in bounds); their outputs are never stored.
     const int64_t lr = lg < nlos ? lg : nlos - 1;
     const int rre = 32 * (la >> 4) + (la & 15);  // real-part row; imaginary row is +16
+    // FP16: per-LOS power-of-two scale that keeps both halves of the split in
+    // half precision's normal range; undone exactly in the epilogue.
+    const float lsc = FP16 ? los_scale[lr] : 1.0f;
     const_f4_ptr bt = (const_f4_ptr)(base + (int64_t)tn * nchan_pad);
 
     // Q/U and channel rotations of one K-step (4 channels of this thread),
@@ -144,6 +148,10 @@ __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
         float yr = __builtin_fmaf(R.u[i], rc, -(R.q[i] * rs));
         xr = flagged ? 0.0f : xr;
         yr = flagged ? 0.0f : yr;
+        if (FP16) {
+            xr *= lsc;
+            yr *= lsc;
+        }
         split2<FP16>(xr, yr, hi[i], lo[i]);
     };
     auto store_t = [&](BBuf& b, const Regs& R) {
@@ -255,6 +263,14 @@ __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
         for (int v = 0; v < 8; ++v) {
             const int i = 8 * (v >> 2) + 4 * half + (v & 3);
             const int64_t l = l0 + 64 * wr + 16 * rb + i;
+            if (FP16) {
+                const float inv = 1.0f / los_scale[l < nlos ? l : nlos - 1];
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb) {
+                    acc[rb][cb][v] *= inv;
+                    acc[rb][cb][v + 8] *= inv;
+                }
+            }
             const int64_t off = l * nphi + nc;
             float* fq = Fq + off;
             float* fu = Fu + off;
@@ -323,6 +339,52 @@ __global__ void factor_tables_kernel(const double* __restrict__ bj, const float*
     }
 }
 
+// Per-LOS power-of-two scale for the FP16 split: M = K max_j w_j max(|Q_j|, |U_j|)
+// bounds the rotated components up to a factor sqrt 2; the scale 2^(13 - E), with
+// M < 2^E, keeps them below 2^14 (half precision's largest finite value is
+// 65504), so hi and lo stay normal down to 2^-10 of the LOS's largest value.
+// Non-finite values are ignored (they poison their LOS anyway).
+template <int LAYOUT>
+__global__ __launch_bounds__(256) void los_scale_kernel(const float* __restrict__ Q,
+                                                        const float* __restrict__ U,
+                                                        int64_t nlos, int64_t ld, int nchan,
+                                                        const float* __restrict__ wj, float K,
+                                                        float* __restrict__ scale)
+{
+    float m = 0.0f;
+    int64_t l;
+    if (LAYOUT == RMSYNTH_LOS_MAJOR) {
+        // One wave per LOS row.
+        l = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+        if (l >= nlos) return;
+        for (int j = threadIdx.x & 63; j < nchan; j += 64) {
+            const float a = __builtin_fabsf(Q[l * ld + j]), b = __builtin_fabsf(U[l * ld + j]);
+            const float v = wj[j] * __builtin_fmaxf(a, b);
+            if (v <= 3.0e38f) m = __builtin_fmaxf(m, v);
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) m = __builtin_fmaxf(m, __shfl_xor(m, off, 64));
+        if ((threadIdx.x & 63) != 0) return;
+    } else {
+        // One thread per LOS, channel planes read coalesced along LOS.
+        l = (int64_t)blockIdx.x * 256 + threadIdx.x;
+        if (l >= nlos) return;
+        for (int j = 0; j < nchan; ++j) {
+            const float a = __builtin_fabsf(Q[(int64_t)j * ld + l]), b = __builtin_fabsf(U[(int64_t)j * ld + l]);
+            const float v = wj[j] * __builtin_fmaxf(a, b);
+            if (v <= 3.0e38f) m = __builtin_fmaxf(m, v);
+        }
+    }
+    m *= K;
+    int e = 0;
+    if (m > 0.0f) {
+        (void)__builtin_frexpf(m, &e);  // m < 2^e
+        e = 13 - e;
+        e = e < -100 ? -100 : (e > 100 ? 100 : e);
+    }
+    scale[l] = __builtin_ldexpf(1.0f, e);
+}
+
 template <bool FP16>
 hipError_t launch_t(const rmsynth_plan_s& p, const ExecArgs& a)
 {
@@ -337,7 +399,7 @@ hipError_t launch_t(const rmsynth_plan_s& p, const ExecArgs& a)
 #define RMS_LAUNCH(L, F)                                                                       \
     hipLaunchKernelGGL((synth_factored_kernel<L, FP16, F>), dim3((unsigned)blocks), dim3(256), 0, \
                        a.stream, a.Q, a.U, a.nlos, a.ld, p.nchan, p.d_base, Thi, Tlo,            \
-                       p.nchan_pad, nk, p.nphi, tiles_n, a.Fq, a.Fu, a.Fabs)
+                       p.nchan_pad, nk, p.nphi, tiles_n, a.Fq, a.Fu, a.Fabs, a.los_scale)
     if (a.layout == RMSYNTH_LOS_MAJOR) {
         if (full_k && a.vec4) RMS_LAUNCH(RMSYNTH_LOS_MAJOR, true);
         else RMS_LAUNCH(RMSYNTH_LOS_MAJOR, false);
@@ -350,6 +412,19 @@ hipError_t launch_t(const rmsynth_plan_s& p, const ExecArgs& a)
 }
 
 }  // namespace
+
+hipError_t launch_los_scale(const rmsynth_plan_s& p, const ExecArgs& a)
+{
+    if (a.layout == RMSYNTH_LOS_MAJOR)
+        hipLaunchKernelGGL(los_scale_kernel<RMSYNTH_LOS_MAJOR>, dim3((unsigned)((a.nlos + 3) / 4)),
+                           dim3(256), 0, a.stream, a.Q, a.U, a.nlos, a.ld, p.nchan, p.d_w,
+                           (float)p.K, a.los_scale);
+    else
+        hipLaunchKernelGGL(los_scale_kernel<RMSYNTH_FREQ_MAJOR>, dim3((unsigned)((a.nlos + 255) / 256)),
+                           dim3(256), 0, a.stream, a.Q, a.U, a.nlos, a.ld, p.nchan, p.d_w,
+                           (float)p.K, a.los_scale);
+    return hipGetLastError();
+}
 
 hipError_t launch_synth_factored(const rmsynth_plan_s& p, const ExecArgs& a, int precision)
 {

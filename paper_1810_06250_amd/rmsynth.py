@@ -48,6 +48,21 @@ SIGNATURES = {
     "rmsynth_destroy": (None, [_P]),
     "rmsynth_last_error": (ctypes.c_char_p, []),
     "rmsynth_version": (ctypes.c_char_p, []),
+    # learned gate (include/rmsynth_mlp.h)
+    "rmsynth_mlp_create": (ctypes.c_int, [_I32, _I32, _I32, _P, ctypes.c_float, ctypes.c_uint64,
+                                          ctypes.POINTER(_P)]),
+    "rmsynth_mlp_num_params": (ctypes.c_int, [_P, ctypes.POINTER(_I64)]),
+    "rmsynth_mlp_get_params": (ctypes.c_int, [_P, _P]),
+    "rmsynth_mlp_set_params": (ctypes.c_int, [_P, _P]),
+    "rmsynth_mlp_grad": (ctypes.c_int, [_P, _P, _P, _I64, _P, _P, _P, _P, _P]),
+    "rmsynth_mlp_train_step": (ctypes.c_int, [_P, _P, _P, _I64, _P, _P, ctypes.c_float, _P, _P]),
+    "rmsynth_mlp_infer": (ctypes.c_int, [_P, _P, _P, _I64, _P, _P, _P]),
+    "rmsynth_gate_workspace_size": (ctypes.c_int, [_P, _P, _I64, ctypes.POINTER(_SZ)]),
+    "rmsynth_gate_execute": (ctypes.c_int, [_P, _P, _P, _P, _I64, ctypes.c_float, _P, _P, _P, _P,
+                                            _P, _SZ, _P]),
+    "rmsynth_mlp_save": (ctypes.c_int, [_P, ctypes.c_char_p]),
+    "rmsynth_mlp_load": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(_P)]),
+    "rmsynth_mlp_destroy": (None, [_P]),
 }
 
 _lib = None
@@ -175,6 +190,99 @@ def rmsynth_version() -> str:
     return load_library().rmsynth_version().decode()
 
 
+# ------------------------------------------------------------------ learned gate
+def rmsynth_mlp_create(nchan: int, h1: int, h2: int, weights=None, phi_scale: float = 300.0,
+                       seed: int = 0) -> ctypes.c_void_p:
+    w = None if weights is None else np.ascontiguousarray(np.asarray(weights, dtype=np.float32))
+    if w is not None and w.size != nchan:
+        raise ValueError("weights must have nchan entries")
+    h = ctypes.c_void_p()
+    _check("rmsynth_mlp_create", load_library().rmsynth_mlp_create(
+        int(nchan), int(h1), int(h2), None if w is None else w.ctypes.data_as(_P),
+        float(phi_scale), int(seed) & (2**64 - 1), ctypes.byref(h)))
+    return h
+
+
+def rmsynth_mlp_num_params(mlp) -> int:
+    n = ctypes.c_int64()
+    _check("rmsynth_mlp_num_params", load_library().rmsynth_mlp_num_params(mlp, ctypes.byref(n)))
+    return n.value
+
+
+def rmsynth_mlp_get_params(mlp) -> np.ndarray:
+    out = np.empty(rmsynth_mlp_num_params(mlp), dtype=np.float32)
+    _check("rmsynth_mlp_get_params", load_library().rmsynth_mlp_get_params(
+        mlp, out.ctypes.data_as(_P)))
+    return out
+
+
+def rmsynth_mlp_set_params(mlp, params):
+    p = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+    if p.size != rmsynth_mlp_num_params(mlp):
+        raise ValueError("parameter vector has the wrong length")
+    _check("rmsynth_mlp_set_params", load_library().rmsynth_mlp_set_params(
+        mlp, p.ctypes.data_as(_P)))
+
+
+def rmsynth_mlp_grad(mlp, Q, U, batch: int, phi_label, det_label, grad, loss=None, stream=None):
+    import torch
+    f32 = torch.float32
+    _check("rmsynth_mlp_grad", load_library().rmsynth_mlp_grad(
+        mlp, _dev(Q, "Q", f32), _dev(U, "U", f32), int(batch), _dev(phi_label, "phi_label", f32),
+        _dev(det_label, "det_label", f32), _dev(grad, "grad", f32), _dev(loss, "loss", f32),
+        _stream(stream)))
+
+
+def rmsynth_mlp_train_step(mlp, Q, U, batch: int, phi_label, det_label, lr: float, loss=None,
+                           stream=None):
+    import torch
+    f32 = torch.float32
+    _check("rmsynth_mlp_train_step", load_library().rmsynth_mlp_train_step(
+        mlp, _dev(Q, "Q", f32), _dev(U, "U", f32), int(batch), _dev(phi_label, "phi_label", f32),
+        _dev(det_label, "det_label", f32), float(lr), _dev(loss, "loss", f32), _stream(stream)))
+
+
+def rmsynth_mlp_infer(mlp, Q, U, nlos: int, phi_hat, score, stream=None):
+    import torch
+    f32 = torch.float32
+    _check("rmsynth_mlp_infer", load_library().rmsynth_mlp_infer(
+        mlp, _dev(Q, "Q", f32), _dev(U, "U", f32), int(nlos), _dev(phi_hat, "phi_hat", f32),
+        _dev(score, "score", f32), _stream(stream)))
+
+
+def rmsynth_gate_workspace_size(plan, mlp, nlos: int) -> int:
+    b = ctypes.c_size_t()
+    _check("rmsynth_gate_workspace_size", load_library().rmsynth_gate_workspace_size(
+        plan, mlp, int(nlos), ctypes.byref(b)))
+    return b.value
+
+
+def rmsynth_gate_execute(plan, mlp, Q, U, nlos: int, tau: float, idx, phi_pk, amp, gated,
+                         workspace, workspace_bytes: int, stream=None):
+    import torch
+    f32, i32 = torch.float32, torch.int32
+    _check("rmsynth_gate_execute", load_library().rmsynth_gate_execute(
+        plan, mlp, _dev(Q, "Q", f32), _dev(U, "U", f32), int(nlos), float(tau),
+        _dev(idx, "idx", i32), _dev(phi_pk, "phi_pk", f32), _dev(amp, "amp", f32),
+        _dev(gated, "gated", i32), _dev(workspace, "workspace"), int(workspace_bytes),
+        _stream(stream)))
+
+
+def rmsynth_mlp_save(mlp, path: str):
+    _check("rmsynth_mlp_save", load_library().rmsynth_mlp_save(mlp, os.fsencode(path)))
+
+
+def rmsynth_mlp_load(path: str) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    _check("rmsynth_mlp_load", load_library().rmsynth_mlp_load(os.fsencode(path), ctypes.byref(h)))
+    return h
+
+
+def rmsynth_mlp_destroy(mlp):
+    if mlp:
+        load_library().rmsynth_mlp_destroy(mlp)
+
+
 # ------------------------------------------------------------------ convenience
 class Plan:
     """Owns an rmsynth plan; allocates outputs with torch on the current device."""
@@ -228,4 +336,70 @@ class Plan:
                    u_pk=torch.empty(nlos, dtype=torch.float32, device=dev))
         rmsynth_peaks(self.handle, Fq, Fu, nlos, out["idx"], out["phi_pk"], out["amp"],
                       out["q_pk"], out["u_pk"])
+        return out
+
+
+class Mlp:
+    """Owns a gate network (rmsynth_mlp_*); outputs are torch tensors."""
+
+    def __init__(self, nchan: int = 0, h1: int = 256, h2: int = 256, weights=None,
+                 phi_scale: float = 300.0, seed: int = 0, handle=None):
+        self.handle = handle if handle is not None else rmsynth_mlp_create(
+            nchan, h1, h2, weights, phi_scale, seed)
+        self.nparams = rmsynth_mlp_num_params(self.handle)
+
+    @classmethod
+    def load(cls, path: str) -> "Mlp":
+        return cls(handle=rmsynth_mlp_load(path))
+
+    def save(self, path: str):
+        rmsynth_mlp_save(self.handle, path)
+
+    def close(self):
+        if self.handle:
+            rmsynth_mlp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self) -> np.ndarray:
+        return rmsynth_mlp_get_params(self.handle)
+
+    def set_params(self, params):
+        rmsynth_mlp_set_params(self.handle, params)
+
+    def grad(self, Q, U, phi_label, det_label):
+        import torch
+        g = torch.empty(self.nparams, dtype=torch.float32, device=Q.device)
+        loss = torch.empty(1, dtype=torch.float32, device=Q.device)
+        rmsynth_mlp_grad(self.handle, Q, U, Q.shape[0], phi_label, det_label, g, loss)
+        return g, loss
+
+    def train_step(self, Q, U, phi_label, det_label, lr: float, loss=None):
+        rmsynth_mlp_train_step(self.handle, Q, U, Q.shape[0], phi_label, det_label, lr, loss)
+
+    def infer(self, Q, U):
+        import torch
+        n = Q.shape[0]
+        phi_hat = torch.empty(n, dtype=torch.float32, device=Q.device)
+        score = torch.empty_like(phi_hat)
+        rmsynth_mlp_infer(self.handle, Q, U, n, phi_hat, score)
+        return phi_hat, score
+
+    def gate(self, plan: "Plan", Q, U, tau: float):
+        import torch
+        n = Q.shape[0]
+        dev = Q.device
+        out = dict(idx=torch.empty(n, dtype=torch.int32, device=dev),
+                   phi_pk=torch.empty(n, dtype=torch.float32, device=dev),
+                   amp=torch.empty(n, dtype=torch.float32, device=dev),
+                   gated=torch.empty(n, dtype=torch.int32, device=dev))
+        nb = rmsynth_gate_workspace_size(plan.handle, self.handle, n)
+        ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+        rmsynth_gate_execute(plan.handle, self.handle, Q, U, n, tau, out["idx"], out["phi_pk"],
+                             out["amp"], out["gated"], ws, nb)
         return out

@@ -6,6 +6,7 @@ import numpy as np
 PREC_TOL = {  # per-LOS bound on max_k |F_gpu - F_oracle| / max_k |F_oracle|
     "fp32": 1e-5,
     "bf16x3": 1e-5,
+    "fp16x3": 1e-5,
 }
 
 # Bound for grids too short for max_k |F| to be representative (a handful of
@@ -16,6 +17,7 @@ PREC_TOL = {  # per-LOS bound on max_k |F_gpu - F_oracle| / max_k |F_oracle|
 SCALE_TOL = {
     "fp32": 1e-5,
     "bf16x3": 3 * 2.0 ** -16,
+    "fp16x3": 1e-5,   # 11-bit halves: split residuals 2^-22, below FP32 rounding effects
 }
 
 

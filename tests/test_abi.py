@@ -1,7 +1,8 @@
 """Host-side checks of the C ABI that need no GPU: the library loads, exports
-every symbol include/rmsynth.h declares, and rejects invalid arguments before
+every symbol the headers under include/ declare, and rejects invalid arguments before
 touching the device."""
 import ctypes
+import glob
 import math
 import os
 import re
@@ -12,13 +13,15 @@ import pytest
 import paper_1810_06250_amd as rs
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "rmsynth.h")
+HEADERS = sorted(glob.glob(os.path.join(ROOT, "include", "*.h")))
 
 
 def _declared():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(rmsynth_[a-z_0-9]+)\s*\(", text)))
+    names = set()
+    for h in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names.update(re.findall(r"\b(rmsynth_[a-z_0-9]+)\s*\(", text))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")
@@ -110,3 +113,51 @@ def test_error_raises_in_binding(lib):
     with pytest.raises(rs.RmsynthError) as ei:
         rs.rmsynth_plan(np.ones(3), np.zeros(3), np.zeros(2))
     assert ei.value.code == rs.rmsynth.RMSYNTH_EINVAL
+
+
+def _mlp_rc(nchan, h1, h2, weights=None, phi_scale=300.0):
+    h = ctypes.c_void_p()
+    w = None
+    if weights is not None:
+        w = np.ascontiguousarray(weights, dtype=np.float32)
+    rc = rs.load_library().rmsynth_mlp_create(nchan, h1, h2,
+                                              None if w is None else w.ctypes.data, phi_scale, 0,
+                                              ctypes.byref(h))
+    return rc, h
+
+
+@pytest.mark.parametrize("args", [
+    (0, 64, 64), (10, 0, 64), (10, 65, 64), (10, 64, 100), (10, 64, 8192),
+])
+def test_mlp_create_rejects_bad_shapes(lib, args):
+    rc, h = _mlp_rc(*args)
+    assert rc == rs.RMSYNTH_EINVAL and not h.value
+    assert "rmsynth_mlp_create" in rs.rmsynth_last_error()
+
+
+def test_mlp_create_rejects_bad_weights_and_scale(lib):
+    assert _mlp_rc(4, 64, 64, weights=[1, -1, 1, 1])[0] == rs.RMSYNTH_EINVAL
+    assert _mlp_rc(4, 64, 64, weights=[1, np.nan, 1, 1])[0] == rs.RMSYNTH_EINVAL
+    assert _mlp_rc(4, 64, 64, phi_scale=0.0)[0] == rs.RMSYNTH_EINVAL
+    assert _mlp_rc(4, 64, 64, phi_scale=float("inf"))[0] == rs.RMSYNTH_EINVAL
+
+
+def test_mlp_calls_reject_null_handles(lib):
+    n = ctypes.c_int64()
+    assert lib.rmsynth_mlp_num_params(None, ctypes.byref(n)) == rs.RMSYNTH_EINVAL
+    assert lib.rmsynth_mlp_train_step(None, None, None, 1, None, None, 1e-3, None, None) == rs.RMSYNTH_EINVAL
+    assert lib.rmsynth_mlp_infer(None, None, None, 1, None, None, None) == rs.RMSYNTH_EINVAL
+    assert lib.rmsynth_gate_execute(None, None, None, None, 1, 0.5, None, None, None, None, None, 0,
+                                    None) == rs.RMSYNTH_EINVAL
+    b = ctypes.c_size_t()
+    assert lib.rmsynth_gate_workspace_size(None, None, 1, ctypes.byref(b)) == rs.RMSYNTH_EINVAL
+    lib.rmsynth_mlp_destroy(None)
+
+
+def test_mlp_load_rejects_missing_and_foreign_files(lib, tmp_path):
+    h = ctypes.c_void_p()
+    assert lib.rmsynth_mlp_load(str(tmp_path / "none.bin").encode(), ctypes.byref(h)) == rs.RMSYNTH_EINVAL
+    bad = tmp_path / "bad.bin"
+    bad.write_bytes(b"NOTANMLP" + bytes(64))
+    assert lib.rmsynth_mlp_load(str(bad).encode(), ctypes.byref(h)) == rs.RMSYNTH_EINVAL
+    assert not h.value

@@ -16,7 +16,7 @@ from gpu_util import PREC_TOL, SCALE_TOL, dev32, host, note
 
 pytestmark = pytest.mark.gpu
 
-PRECS = {"fp32": rs.RMSYNTH_FP32, "bf16x3": rs.RMSYNTH_SPLIT_BF16}
+PRECS = {"fp32": rs.RMSYNTH_FP32, "bf16x3": rs.RMSYNTH_SPLIT_BF16, "fp16x3": rs.RMSYNTH_SPLIT_FP16}
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -241,6 +241,7 @@ def _full_size(name, prec_list, nsub):
     for prec in prec_list:
         note(f"{name}: execute {prec}")
         plan.execute(cube["Q"], cube["U"], cube["layout"], PRECS[prec], out=(Fq, Fu, None))
+        torch.cuda.synchronize()
         pk = plan.peaks(Fq, Fu)
         gq, gu = host(Fq[subt]), host(Fu[subt])
         err = oracle.per_los_error(gq, gu, rq, ru)
@@ -257,15 +258,15 @@ def _full_size(name, prec_list, nsub):
 
 def test_c2_full_size_sampled():
     """512^2 LOS, 800 channels (40 flagged), 1001 phi, frequency-major."""
-    _full_size("c2", ["fp32", "bf16x3"], 2048)
+    _full_size("c2", ["fp32", "bf16x3", "fp16x3"], 2048)
 
 
 def test_c3_full_size_sampled():
     """1024^2 LOS, 400 channels, 2001 phi, LOS-major: the benchmark workload."""
-    _full_size("c3", ["bf16x3", "fp32"], 4096)
+    _full_size("c3", ["bf16x3", "fp32", "fp16x3"], 4096)
 
 
-@pytest.mark.parametrize("prec", list(PRECS))
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
 @pytest.mark.parametrize("layout", [LOS_MAJOR, FREQ_MAJOR], ids=["los", "freq"])
 def test_nonuniform_phi_grid(prec, layout):
     """An irregular phi grid takes the per-element phase generator instead of
@@ -280,3 +281,42 @@ def test_nonuniform_phi_grid(prec, layout):
     out = _run(plan, dev32(Q32), dev32(U32), layout, PRECS[prec])
     _check(out, Q32.astype(np.float64), U32.astype(np.float64), c["lambda2"], c["weights"],
            phi, layout, PREC_TOL[prec])
+
+
+def test_fp16_split_needs_uniform_grid_and_workspace():
+    """The FP16 split keeps a per-LOS scale in the caller's workspace and is
+    only offered on uniform phi grids."""
+    import torch
+    c = make_small_cube(8, 32, 9, seed=2)
+    Q = dev32(c["Q"])
+    F = torch.empty((8, 40), dtype=torch.float32, device="cuda")
+    rng = np.random.default_rng(3)
+    plan = rs.Plan(c["lambda2"], c["weights"], np.sort(rng.uniform(-50, 50, 40)))
+    with pytest.raises(rs.RmsynthError) as ei:
+        rs.rmsynth_execute(plan.handle, Q, Q, 8, LOS_MAJOR, rs.RMSYNTH_SPLIT_FP16, F, F)
+    assert ei.value.code == rs.rmsynth.RMSYNTH_EUNSUPPORTED
+    plan = rs.Plan(c["lambda2"], c["weights"], np.linspace(-50, 50, 40))
+    need = rs.rmsynth_workspace_size(plan.handle, 8, LOS_MAJOR, rs.RMSYNTH_SPLIT_FP16)
+    assert need >= 8 * 4
+    with pytest.raises(rs.RmsynthError) as ei:
+        rs.rmsynth_execute(plan.handle, Q, Q, 8, LOS_MAJOR, rs.RMSYNTH_SPLIT_FP16, F, F)
+    assert ei.value.code == rs.rmsynth.RMSYNTH_EWORKSPACE
+    small = torch.empty(4, dtype=torch.uint8, device="cuda")
+    with pytest.raises(rs.RmsynthError) as ei:
+        rs.rmsynth_execute(plan.handle, Q, Q, 8, LOS_MAJOR, rs.RMSYNTH_SPLIT_FP16, F, F,
+                           workspace=small, workspace_bytes=4)
+    assert ei.value.code == rs.rmsynth.RMSYNTH_EWORKSPACE
+
+
+def test_fp16_split_wide_dynamic_range():
+    """Per-LOS scaling: LOS whose values differ by 1e8 in size are all
+    transformed to FP32-like accuracy."""
+    note("fp16x3 dynamic range")
+    c = make_small_cube(96, 160, 257, seed=31, nsrc=10)
+    scales = 10.0 ** np.linspace(-6, 2, 96)
+    Q = np.float32(c["Q"] * scales[:, None])
+    U = np.float32(c["U"] * scales[:, None])
+    plan = rs.Plan(c["lambda2"], c["weights"], c["phi"])
+    out = _run(plan, dev32(Q), dev32(U), LOS_MAJOR, rs.RMSYNTH_SPLIT_FP16)
+    _check(out, Q.astype(np.float64), U.astype(np.float64), c["lambda2"], c["weights"], c["phi"],
+           LOS_MAJOR, PREC_TOL["fp16x3"])
