@@ -27,6 +27,24 @@ MFMA_FLOP_PER_SAMPLE = {"bf16x3": 24.0, "fp16x3": 24.0, "fp32": 8.0}
 HBM_PEAK_GBS = 8000.0
 METRIC = "LOS·chan·φ Gsamples/s + % MFMA peak, split-BF16 vs FP32 at ≤1e-5 rel err"
 
+# HBM bytes per launch of the dominant kernel, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE counter runs scaled by a plain 1 GiB copy (FETCH x 2.0, WRITE x 1.0),
+# keyed by (workload, precision, sha256 prefix of the kernel source they were
+# taken on).  A changed kernel source reports null until counters are retaken.
+KERNEL_SRC = os.path.join(ROOT, "paper_1810_06250_amd", "csrc", "synth_factored.hip")
+TRAFFIC = {
+    ("c3", "bf16x3", "9f214bb72bf5960f"): 2.0 * 6670351 * 1024 + 1.0 * 25248864 * 1024,
+}
+
+
+def measured_traffic(workload, precision):
+    import hashlib
+    try:
+        digest = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    return TRAFFIC.get((workload, precision, digest))
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -206,7 +224,9 @@ def main():
         "kernels": {"execute_ms": ex_ms, "peaks_ms": pk_ms,
                     "peaks_hbm_gbs": 8.0 * nlos * nphi / (pk_ms * 1e-3) / 1e9},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak,
+                     "traffic": measured_traffic(args.workload, args.precision),
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE)",
                      "per_unit": f"{MFMA_FLOP_PER_SAMPLE[args.precision]:g} MFMA flop per "
                                  f"LOS*channel*phi sample x {samples} samples per launch"},
         "effective_fp32_tflops": 8.0 * samples / (ex_ms * 1e-3) / 1e12,
