@@ -99,9 +99,10 @@ int rmsynth_plan_info(rmsynth_plan_t plan, double* K, double* lambda0_sq,
 
 /*
  * rmsynth_workspace_size -- device workspace rmsynth_execute needs for `nlos`
- * LOS in the given layout and precision.  The current kernels read Q/U in
- * place and need none (*bytes = 0); the argument pair exists so that callers
- * stay valid when a path gains one.
+ * LOS in the given layout and precision.  FP32 and the bfloat16 split read
+ * Q/U in place and need none (*bytes = 0).  The FP16 split keeps one FP32
+ * power-of-two scale per LOS (so that every LOS uses the half range without
+ * overflow): round_up(4 max(nlos, 1), 256) bytes.
  */
 int rmsynth_workspace_size(rmsynth_plan_t plan, int64_t nlos, int32_t layout,
                            int32_t precision, size_t* bytes);
@@ -126,9 +127,11 @@ int rmsynth_rmsf(rmsynth_plan_t plan, float* R_re, float* R_im, void* stream);
  *   workspace, workspace_bytes: device scratch of at least
  *            rmsynth_workspace_size() bytes (may be NULL when that is 0).
  * A LOS whose unflagged channels hold a non-finite value gets non-finite
- * outputs; other LOS are unaffected.
+ * outputs; other LOS are unaffected.  RMSYNTH_SPLIT_FP16 needs a uniform phi
+ * grid (EUNSUPPORTED otherwise); the workspace is overwritten, and calls that
+ * share one workspace must not overlap.
  * Errors: EINVAL (NULL buffers with nlos > 0, bad layout/precision, wrong
- * device current), EWORKSPACE, EHIP (launch failure).
+ * device current), EUNSUPPORTED, EWORKSPACE, EHIP (launch failure).
  */
 int rmsynth_execute(rmsynth_plan_t plan, const float* Q, const float* U, int64_t nlos,
                     int32_t layout, int32_t precision,

@@ -3,7 +3,7 @@
  * (gfx950).
  *
  * The paper evaluates the Faraday dispersion function of eq. (15) for every
- * line of sight (Sect. 3, "for all LOS").  When most lines of sight hold no
+ * line of sight of the cube (Sect. 3).  When most lines of sight hold no
  * polarised source, a small network that looks at the Q/U spectrum can pick
  * the lines of sight worth the fine-grid synthesis; the others report the
  * network's estimate.  The network is not part of the paper: this header is
@@ -122,6 +122,57 @@ int rmsynth_gate_workspace_size(rmsynth_plan_t plan, rmsynth_mlp_t mlp, int64_t 
 int rmsynth_gate_execute(rmsynth_plan_t plan, rmsynth_mlp_t mlp, const float* Q, const float* U,
                          int64_t nlos, float tau, int32_t* idx, float* phi_pk, float* amp,
                          int32_t* gated, void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * Training data.  Synthetic spectra of the sky model of Section 2.1: a
+ * Faraday-thin screen P0 exp(2i(chi0 + phi0 lambda^2)) (eqs. (1), (3)), two
+ * such screens, or a Burn slab of width W, P0 exp(2i(chi0 + phic lambda^2))
+ * sin(W lambda^2)/(W lambda^2) (eq. (4)), plus N(0, sigma^2) noise on every
+ * channel and Stokes parameter.  P0, phi0, W are uniform over the given
+ * ranges, chi0 uniform over [0, pi).  Draws come from Philox4x32-10 (Salmon
+ * et al., SC 2011) addressed by (seed, global line-of-sight index), so a line
+ * of sight has the same content whatever batch makes it:
+ *   counters (0, g_lo, g_hi, 0) class, (1 + c, g_lo, g_hi, 0) component c,
+ *   (m, g_lo, g_hi, 1) noise of channels 2m and 2m + 1;
+ *   32-bit word x -> u = (floor(x / 2^9) + 1/2) 2^-23;
+ *   class 0 (noise only) if u < frac_noise, 1 (one screen) if
+ *   u < frac_noise + frac_thin1, 2 (two screens) if below that + frac_thin2,
+ *   else 3 (slab);  component words -> P0, phi0, chi0, W in that order;
+ *   noise by Box-Muller, (r cos t, r sin t) -> (Q, U), r = sqrt(-2 ln u0),
+ *   t = 2 pi u1 for channel 2m and (u2, u3) for channel 2m + 1.
+ * The model is evaluated in FP64 and rounded to FP32 once.  Labels come from
+ * the transform itself: rmsynth_execute (FP32 path) on the plan's grid and
+ * rmsynth_peaks; phi_label = phi at the peak, det_label = 1 iff the peak
+ * |F| >= det_threshold (0 for a line of sight with non-finite input).
+ */
+typedef struct rmsynth_train_spec {
+    double frac_noise, frac_thin1, frac_thin2;  /* class fractions; slabs get the rest */
+    double p0_lo, p0_hi;                        /* polarised amplitude, >= 0 */
+    double phi_lo, phi_hi;                      /* Faraday depth of the components */
+    double w_lo, w_hi;                          /* slab width, > 0 */
+    double sigma;                               /* noise per channel and Stokes, >= 0 */
+    double det_threshold;                       /* detection threshold on the peak |F| */
+} rmsynth_train_spec;
+
+/* rmsynth_train_workspace_size -- workspace rmsynth_synth_training needs to
+ * label nlos lines of sight (0 when no labels are asked for is also fine). */
+int rmsynth_train_workspace_size(rmsynth_plan_t plan, int64_t nlos, size_t* bytes);
+
+/*
+ * rmsynth_synth_training -- lines of sight first_los .. first_los + nlos - 1
+ * of the stream `seed`, on the plan's channels (its lambda^2).
+ *   Q, U        device [nlos][nchan] float, written
+ *   phi_label, det_label  device [nlos] float or both NULL (no labelling,
+ *               no workspace needed)
+ *   cls         device [nlos] int32 or NULL: class 0..3
+ *   truth       device [nlos][4] float or NULL: (phi0, P0) of components 0
+ *               and 1, NaN where absent
+ * Errors: EINVAL (bad spec, NULL Q/U, first_los < 0), EWORKSPACE, EHIP.
+ */
+int rmsynth_synth_training(rmsynth_plan_t plan, const rmsynth_train_spec* spec, uint64_t seed,
+                           int64_t first_los, int64_t nlos, float* Q, float* U, float* phi_label,
+                           float* det_label, int32_t* cls, float* truth, void* workspace,
+                           size_t workspace_bytes, void* stream);
 
 /*
  * rmsynth_mlp_save / rmsynth_mlp_load -- binary file with the shape, channel

@@ -42,7 +42,7 @@ namespace {
 void free_plan(rmsynth_plan_s* p)
 {
     if (!p) return;
-    void* bufs[] = {p->d_b, p->d_w, p->d_phi, p->d_base, p->d_Tbf[0], p->d_Tbf[1],
+    void* bufs[] = {p->d_b, p->d_lambda2, p->d_w, p->d_phi, p->d_base, p->d_Tbf[0], p->d_Tbf[1],
                     p->d_Thf[0], p->d_Thf[1], p->d_Tf32};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
@@ -156,13 +156,15 @@ int rmsynth_plan(const double* lambda2, const double* weights, int32_t nchan, co
 
     if ((e = hipMalloc(&p->d_b, sizeof(double) * p->nchan_pad)) != hipSuccess ||
         (e = hipMalloc(&p->d_w, sizeof(float) * p->nchan_pad)) != hipSuccess ||
-        (e = hipMalloc(&p->d_phi, sizeof(double) * p->nphi_pad)) != hipSuccess) {
+        (e = hipMalloc(&p->d_phi, sizeof(double) * p->nphi_pad)) != hipSuccess ||
+        (e = hipMalloc(&p->d_lambda2, sizeof(double) * nchan)) != hipSuccess) {
         free_plan(p);
         return rms_fail(RMSYNTH_ENOMEM, "rmsynth_plan: hipMalloc: %s", hipGetErrorString(e));
     }
     if ((e = hipMemcpy(p->d_b, hb.data(), sizeof(double) * p->nchan_pad, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(p->d_w, hw.data(), sizeof(float) * p->nchan_pad, hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(p->d_phi, hphi.data(), sizeof(double) * p->nphi_pad, hipMemcpyHostToDevice)) != hipSuccess) {
+        (e = hipMemcpy(p->d_phi, hphi.data(), sizeof(double) * p->nphi_pad, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(p->d_lambda2, lambda2, sizeof(double) * nchan, hipMemcpyHostToDevice)) != hipSuccess) {
         free_plan(p);
         return rms_hip_fail(e, "rmsynth_plan: hipMemcpy");
     }

@@ -27,6 +27,7 @@ struct rmsynth_plan_s {
     double K, lambda0_sq, fwhm_est, phimax_est;
     double phi_absmax;   // largest |phi_k| of the grid
     double* d_b;
+    double* d_lambda2;   // [nchan] lambda^2 as given
     float* d_w;
     double* d_phi;
     // Factored phase tables, present when the phi grid is uniform

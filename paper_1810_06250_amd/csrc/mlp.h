@@ -35,3 +35,17 @@ hipError_t gate_launch_gather(const float* Q, const float* U, const int64_t* lis
 hipError_t gate_launch_scatter(const int64_t* list, int64_t n, const int32_t* gidx,
                                const float* gphi, const float* gamp, int32_t* idx, float* phi_pk,
                                float* amp, hipStream_t s);
+
+// Training-data synthesis (train.hip).  Uniform ranges [lo, hi]; class
+// thresholds f0 < f1 < f2 are the cumulative fractions of noise-only, one-
+// screen and two-screen lines of sight (the rest are slabs).
+struct TrainSpecDev {
+    double f0, f1, f2;
+    double p0_lo, p0_hi, phi_lo, phi_hi, w_lo, w_hi;
+    double sigma;
+};
+hipError_t train_launch_spectra(const double* lambda2, int nchan, const TrainSpecDev& s, uint64_t seed,
+                                int64_t first, int64_t nlos, float* Q, float* U, int32_t* cls,
+                                float* truth, hipStream_t st);
+hipError_t train_launch_labels(const int32_t* idx, const float* phi_pk, const float* amp, int64_t n,
+                               float thr, float* phi_label, float* det_label, hipStream_t st);

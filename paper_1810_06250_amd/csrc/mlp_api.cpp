@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <vector>
@@ -516,6 +517,103 @@ int rmsynth_gate_execute(rmsynth_plan_t p, rmsynth_mlp_t m, const float* Q, cons
         if (int rc = rmsynth_peaks(p, Fq, Fu, n, gidx, gphi, gamp, nullptr, nullptr, stream)) return rc;
         if ((e = gate_launch_scatter(list + r0, n, gidx, gphi, gamp, idx, phi_pk, amp, s)) != hipSuccess)
             return rms_hip_fail(e, who);
+    }
+    return rms_ok();
+}
+
+// Labelling workspace: Fq, Fu [C][nphi] | idx, phi, amp [C], C = min(nlos, kGateChunk).
+static size_t train_ws(const rmsynth_plan_s* p, int64_t nlos, int64_t* chunk)
+{
+    const int64_t C = std::max<int64_t>(1, std::min(nlos, kGateChunk));
+    if (chunk) *chunk = C;
+    return 2 * (size_t)round_up(4 * C * (int64_t)p->nphi, 256) + 3 * (size_t)round_up(4 * C, 256);
+}
+
+int rmsynth_train_workspace_size(rmsynth_plan_t p, int64_t nlos, size_t* bytes)
+{
+    if (!p || !bytes) return rms_fail(RMSYNTH_EINVAL, "rmsynth_train_workspace_size: NULL argument");
+    if (nlos < 0) return rms_fail(RMSYNTH_EINVAL, "rmsynth_train_workspace_size: nlos=%lld", (long long)nlos);
+    *bytes = train_ws(p, nlos, nullptr);
+    return rms_ok();
+}
+
+int rmsynth_synth_training(rmsynth_plan_t p, const rmsynth_train_spec* sp, uint64_t seed,
+                           int64_t first_los, int64_t nlos, float* Q, float* U, float* phi_label,
+                           float* det_label, int32_t* cls, float* truth, void* workspace,
+                           size_t workspace_bytes, void* stream)
+{
+    const char* who = "rmsynth_synth_training";
+    if (!p || !sp) return rms_fail(RMSYNTH_EINVAL, "%s: plan or spec is NULL", who);
+    if (nlos < 0 || first_los < 0 || first_los > INT64_MAX - nlos)
+        return rms_fail(RMSYNTH_EINVAL, "%s: first_los=%lld nlos=%lld", who, (long long)first_los,
+                        (long long)nlos);
+    const double fr[3] = {sp->frac_noise, sp->frac_thin1, sp->frac_thin2};
+    double fsum = 0.0;
+    for (double f : fr) {
+        if (!(f >= 0.0 && f <= 1.0)) return rms_fail(RMSYNTH_EINVAL, "%s: class fraction %g", who, f);
+        fsum += f;
+    }
+    if (fsum > 1.0 + 1e-12) return rms_fail(RMSYNTH_EINVAL, "%s: class fractions sum to %g", who, fsum);
+    auto range_ok = [](double lo, double hi) { return std::isfinite(lo) && std::isfinite(hi) && lo <= hi; };
+    if (!range_ok(sp->p0_lo, sp->p0_hi) || sp->p0_lo < 0.0)
+        return rms_fail(RMSYNTH_EINVAL, "%s: P0 range [%g, %g]", who, sp->p0_lo, sp->p0_hi);
+    if (!range_ok(sp->phi_lo, sp->phi_hi))
+        return rms_fail(RMSYNTH_EINVAL, "%s: phi range [%g, %g]", who, sp->phi_lo, sp->phi_hi);
+    if (!range_ok(sp->w_lo, sp->w_hi) || !(sp->w_lo > 0.0))
+        return rms_fail(RMSYNTH_EINVAL, "%s: slab width range [%g, %g]", who, sp->w_lo, sp->w_hi);
+    if (!std::isfinite(sp->sigma) || sp->sigma < 0.0)
+        return rms_fail(RMSYNTH_EINVAL, "%s: sigma=%g", who, sp->sigma);
+    if (std::isnan(sp->det_threshold)) return rms_fail(RMSYNTH_EINVAL, "%s: det_threshold is NaN", who);
+    if (nlos == 0) return rms_ok();
+    if (!Q || !U) return rms_fail(RMSYNTH_EINVAL, "%s: NULL Q or U", who);
+    const bool want_labels = phi_label || det_label;
+    int64_t C = 0;
+    const size_t need = want_labels ? train_ws(p, nlos, &C) : 0;
+    if (want_labels && (!workspace || workspace_bytes < need))
+        return rms_fail(RMSYNTH_EWORKSPACE, "%s: needs %zu workspace bytes, got %zu", who, need,
+                        workspace ? workspace_bytes : (size_t)0);
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return rms_hip_fail(e, "hipGetDevice");
+    if (dev != p->device)
+        return rms_fail(RMSYNTH_EINVAL, "%s: plan was created on device %d but device %d is current",
+                        who, p->device, dev);
+    hipStream_t s = (hipStream_t)stream;
+    TrainSpecDev d{};
+    d.f0 = fr[0];
+    d.f1 = fr[0] + fr[1];
+    d.f2 = fr[0] + fr[1] + fr[2];
+    d.p0_lo = sp->p0_lo; d.p0_hi = sp->p0_hi;
+    d.phi_lo = sp->phi_lo; d.phi_hi = sp->phi_hi;
+    d.w_lo = sp->w_lo; d.w_hi = sp->w_hi;
+    d.sigma = sp->sigma;
+    // Launch in batches that keep the grid within its limit.
+    const int64_t max_los = int64_t(1) << 30;
+    for (int64_t l0 = 0; l0 < nlos; l0 += max_los) {
+        const int64_t n = std::min(max_los, nlos - l0);
+        e = train_launch_spectra(p->d_lambda2, p->nchan, d, seed, first_los + l0, n,
+                                 Q + l0 * p->nchan, U + l0 * p->nchan, cls ? cls + l0 : nullptr,
+                                 truth ? truth + 4 * l0 : nullptr, s);
+        if (e != hipSuccess) return rms_hip_fail(e, who);
+    }
+    if (!want_labels) return rms_ok();
+    char* ws = static_cast<char*>(workspace);
+    float* Fq = reinterpret_cast<float*>(ws);
+    float* Fu = reinterpret_cast<float*>(ws + round_up(4 * C * (int64_t)p->nphi, 256));
+    char* tail = ws + 2 * round_up(4 * C * (int64_t)p->nphi, 256);
+    auto* idx = reinterpret_cast<int32_t*>(tail);
+    auto* phk = reinterpret_cast<float*>(tail + round_up(4 * C, 256));
+    auto* amp = reinterpret_cast<float*>(tail + 2 * round_up(4 * C, 256));
+    for (int64_t l0 = 0; l0 < nlos; l0 += C) {
+        const int64_t n = std::min(C, nlos - l0);
+        if (int rc = rmsynth_execute(p, Q + l0 * p->nchan, U + l0 * p->nchan, n, RMSYNTH_LOS_MAJOR,
+                                     RMSYNTH_FP32, Fq, Fu, nullptr, nullptr, 0, stream))
+            return rc;
+        if (int rc = rmsynth_peaks(p, Fq, Fu, n, idx, phk, amp, nullptr, nullptr, stream)) return rc;
+        e = train_launch_labels(idx, phk, amp, n, (float)sp->det_threshold,
+                                phi_label ? phi_label + l0 : nullptr,
+                                det_label ? det_label + l0 : nullptr, s);
+        if (e != hipSuccess) return rms_hip_fail(e, who);
     }
     return rms_ok();
 }

@@ -60,6 +60,9 @@ SIGNATURES = {
     "rmsynth_gate_workspace_size": (ctypes.c_int, [_P, _P, _I64, ctypes.POINTER(_SZ)]),
     "rmsynth_gate_execute": (ctypes.c_int, [_P, _P, _P, _P, _I64, ctypes.c_float, _P, _P, _P, _P,
                                             _P, _SZ, _P]),
+    "rmsynth_train_workspace_size": (ctypes.c_int, [_P, _I64, ctypes.POINTER(_SZ)]),
+    "rmsynth_synth_training": (ctypes.c_int, [_P, _P, ctypes.c_uint64, _I64, _I64, _P, _P, _P, _P,
+                                              _P, _P, _P, _SZ, _P]),
     "rmsynth_mlp_save": (ctypes.c_int, [_P, ctypes.c_char_p]),
     "rmsynth_mlp_load": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(_P)]),
     "rmsynth_mlp_destroy": (None, [_P]),
@@ -268,6 +271,35 @@ def rmsynth_gate_execute(plan, mlp, Q, U, nlos: int, tau: float, idx, phi_pk, am
         _stream(stream)))
 
 
+class TrainSpec(ctypes.Structure):
+    """rmsynth_train_spec: class mix, parameter ranges, noise and detection threshold."""
+    _fields_ = [(n, ctypes.c_double) for n in (
+        "frac_noise", "frac_thin1", "frac_thin2", "p0_lo", "p0_hi", "phi_lo", "phi_hi",
+        "w_lo", "w_hi", "sigma", "det_threshold")]
+
+    def as_dict(self) -> dict:
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+def rmsynth_train_workspace_size(plan, nlos: int) -> int:
+    b = ctypes.c_size_t()
+    _check("rmsynth_train_workspace_size", load_library().rmsynth_train_workspace_size(
+        plan, int(nlos), ctypes.byref(b)))
+    return b.value
+
+
+def rmsynth_synth_training(plan, spec: TrainSpec, seed: int, first_los: int, nlos: int, Q, U,
+                           phi_label=None, det_label=None, cls=None, truth=None, workspace=None,
+                           workspace_bytes: int = 0, stream=None):
+    import torch
+    f32 = torch.float32
+    _check("rmsynth_synth_training", load_library().rmsynth_synth_training(
+        plan, ctypes.byref(spec), int(seed) & (2**64 - 1), int(first_los), int(nlos),
+        _dev(Q, "Q", f32), _dev(U, "U", f32), _dev(phi_label, "phi_label", f32),
+        _dev(det_label, "det_label", f32), _dev(cls, "cls", torch.int32), _dev(truth, "truth", f32),
+        _dev(workspace, "workspace"), int(workspace_bytes), _stream(stream)))
+
+
 def rmsynth_mlp_save(mlp, path: str):
     _check("rmsynth_mlp_save", load_library().rmsynth_mlp_save(mlp, os.fsencode(path)))
 
@@ -337,6 +369,27 @@ class Plan:
         rmsynth_peaks(self.handle, Fq, Fu, nlos, out["idx"], out["phi_pk"], out["amp"],
                       out["q_pk"], out["u_pk"])
         return out
+
+
+def make_training_data(plan: "Plan", spec: TrainSpec, seed: int, first_los: int, nlos: int,
+                       labels: bool = True, extras: bool = False, device="cuda"):
+    """Allocate and fill one batch of training data with rmsynth_synth_training."""
+    import torch
+    out = dict(Q=torch.empty((nlos, plan.nchan), dtype=torch.float32, device=device),
+               U=torch.empty((nlos, plan.nchan), dtype=torch.float32, device=device))
+    ws, nb = None, 0
+    if labels:
+        out["phi_label"] = torch.empty(nlos, dtype=torch.float32, device=device)
+        out["det_label"] = torch.empty(nlos, dtype=torch.float32, device=device)
+        nb = rmsynth_train_workspace_size(plan.handle, nlos)
+        ws = torch.empty(nb, dtype=torch.uint8, device=device)
+    if extras:
+        out["cls"] = torch.empty(nlos, dtype=torch.int32, device=device)
+        out["truth"] = torch.empty((nlos, 4), dtype=torch.float32, device=device)
+    rmsynth_synth_training(plan.handle, spec, seed, first_los, nlos, out["Q"], out["U"],
+                           out.get("phi_label"), out.get("det_label"), out.get("cls"),
+                           out.get("truth"), ws, nb)
+    return out
 
 
 class Mlp:
