@@ -43,7 +43,7 @@ void free_plan(rmsynth_plan_s* p)
 {
     if (!p) return;
     void* bufs[] = {p->d_b, p->d_lambda2, p->d_w, p->d_phi, p->d_base, p->d_Tbf[0], p->d_Tbf[1],
-                    p->d_Thf[0], p->d_Thf[1], p->d_Tf32};
+                    p->d_Thf[0], p->d_Thf[1]};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     delete p;
@@ -71,8 +71,7 @@ int build_factor_tables(rmsynth_plan_s* p)
         (e = hipMalloc(&p->d_Tbf[0], sizeof(uint4) * nT)) != hipSuccess ||
         (e = hipMalloc(&p->d_Tbf[1], sizeof(uint4) * nT)) != hipSuccess ||
         (e = hipMalloc(&p->d_Thf[0], sizeof(uint4) * nT)) != hipSuccess ||
-        (e = hipMalloc(&p->d_Thf[1], sizeof(uint4) * nT)) != hipSuccess ||
-        (e = hipMalloc(&p->d_Tf32, sizeof(float4) * 2 * nT)) != hipSuccess)
+        (e = hipMalloc(&p->d_Thf[1], sizeof(uint4) * nT)) != hipSuccess)
         return rms_fail(RMSYNTH_ENOMEM, "rmsynth_plan: hipMalloc (phase tables): %s", hipGetErrorString(e));
     hipStream_t s = nullptr;
     if ((e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) != hipSuccess)
@@ -113,6 +112,7 @@ int rmsynth_plan(const double* lambda2, const double* weights, int32_t nchan, co
     if (nchan < 1 || nchan > 65536) return rms_fail(RMSYNTH_EINVAL, "rmsynth_plan: nchan=%d", nchan);
     if (nphi < 1 || nphi > (1 << 20)) return rms_fail(RMSYNTH_EINVAL, "rmsynth_plan: nphi=%d", nphi);
     double sw = 0.0, swl = 0.0, lo = INFINITY, hi = -INFINITY;
+    bool any_flagged = false;
     for (int32_t j = 0; j < nchan; ++j) {
         const double w = weights[j], l = lambda2[j];
         if (!std::isfinite(w) || w < 0.0)
@@ -120,6 +120,7 @@ int rmsynth_plan(const double* lambda2, const double* weights, int32_t nchan, co
         if (!std::isfinite(l)) return rms_fail(RMSYNTH_EINVAL, "rmsynth_plan: lambda2 %d is %g", j, l);
         sw += w;
         swl += w * l;
+        if (w == 0.0) any_flagged = true;
         if (w > 0.0) { lo = std::min(lo, l); hi = std::max(hi, l); }
     }
     if (!(sw > 0.0)) return rms_fail(RMSYNTH_EINVAL, "rmsynth_plan: sum of weights is %g", sw);
@@ -134,6 +135,7 @@ int rmsynth_plan(const double* lambda2, const double* weights, int32_t nchan, co
     if (e != hipSuccess) { free_plan(p); return rms_hip_fail(e, "hipGetDevice"); }
     p->nchan = nchan;
     p->nphi = nphi;
+    p->any_flagged = any_flagged;
     p->nchan_pad = (int32_t)round_up(nchan, kChanPad);
     p->nphi_pad = (int32_t)round_up(nphi, kPhiPad);
     p->K = 1.0 / sw;

@@ -32,17 +32,17 @@ struct rmsynth_plan_s {
     double* d_phi;
     // Factored phase tables, present when the phi grid is uniform
     // (phi_k = phi_0 + k dphi).  With tiles of kFactorTile phi,
-    //   exp(-i theta_{j, k0+m}) = exp(-i theta_{j, k0}) * exp(-2i a_j m dphi):
+    //   exp(-i theta_{j,k0+m}) = exp(-i theta_{j,k0}) * exp(-2i a_j m dphi):
     //   d_base [ftiles][nchan_pad] float2  K w_j (cos, sin)(theta_{j,k0}), k0 = tile start
-    //   d_T{fmt}[hi/lo] [nchan_pad/4][kFactorTile] uint4: 4 channels x (cos, sin)
-    //                   of 2 a_j m dphi, split into 16-bit hi/lo
+    //   d_T{bf,hf}[hi/lo] [nchan_pad/4][kFactorTile] uint4: 4 channels x (cos, sin)
+    //                   of 2 a_j m dphi, split into 16-bit hi/lo (bfloat16, half)
     bool uniform;
     double phi0, dphi;
     int32_t ftiles;
     float2* d_base;
     uint4* d_Tbf[2];
     uint4* d_Thf[2];
-    float4* d_Tf32;      // [nchan_pad/2][kFactorTile]: 2 channels x (cos, sin), FP32
+    bool any_flagged;    // some channel has weight 0
 };
 
 constexpr int kFactorTile = 128;  // phi per tile of the factored kernels

@@ -271,6 +271,188 @@ __global__ __launch_bounds__(256) void mean_kernel(const float* __restrict__ x, 
     if (threadIdx.x == 0) *out = part[0] / (float)n;
 }
 
+// ----------------------------------------------------------------- fused inference
+// One workgroup per 64 LOS, hidden widths 256 and 256: per-LOS rms, then
+// layer 1 with the input tile normalised and rounded to half on its way into
+// LDS (the same FP32 expression as input_kernel), layer 2 from the half h1
+// tile in LDS, and the head, without any activation leaving the CU.  Weights
+// are read from L2 straight into the B-operand registers.  z1 and z2 are
+// bitwise those of the unfused GEMMs (same MFMA k order); the head sums its
+// 256 products in another order.
+constexpr int FR = 64;                 // LOS per workgroup
+constexpr int FH = 256;                // hidden width
+constexpr int FHS = FH + 8;            // LDS row stride of h1 (halves)
+
+__global__ __launch_bounds__(256, 2) void infer_fused_kernel(
+    const float* __restrict__ Q, const float* __restrict__ U, int64_t nlos, int nchan,
+    const float* __restrict__ w, int nin_pad, const _Float16* __restrict__ W1,
+    const float* __restrict__ b1, const _Float16* __restrict__ W2, const float* __restrict__ b2,
+    const _Float16* __restrict__ W3, const float* __restrict__ b3, float phi_scale,
+    float* __restrict__ phi_hat, float* __restrict__ score)
+{
+    __shared__ float inv_rms[FR];
+    __shared__ _Float16 sx[FR][GRS];     // one K-step of the input tile
+    __shared__ _Float16 sh[FR][FHS];     // h1
+    __shared__ float part[4][FR][2];     // head partial sums per wave
+    const int t = threadIdx.x, lane = t & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int64_t r0 = (int64_t)blockIdx.x * FR;
+
+    // rms of each row (rows past the end read the last LOS; never stored).
+    for (int i = 0; i < FR / 4; ++i) {
+        const int row = wave * (FR / 4) + i;
+        const int64_t l = r0 + row < nlos ? r0 + row : nlos - 1;
+        const float* q = Q + l * nchan;
+        const float* u = U + l * nchan;
+        float ss = 0.0f;
+        for (int j = lane; j < nchan; j += 64) {
+            const float a = w[j] == 0.0f ? 0.0f : w[j] * q[j];
+            const float c = w[j] == 0.0f ? 0.0f : w[j] * u[j];
+            ss = __builtin_fmaf(a, a, __builtin_fmaf(c, c, ss));
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off, 64);
+        if (lane == 0)
+            inv_rms[row] = ss > 0.0f ? 1.0f / sqrtf(ss / (float)(2 * nchan)) : (ss == 0.0f ? 0.0f : ss);
+    }
+    __syncthreads();
+
+    const int r = lane & 31, hsel = lane >> 5;
+    const int ncol = 64 * wave;              // this wave's 64 hidden units
+    f32x16_t acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
+
+    // Layer 1.  Loader: row t / 4, 8 consecutive inputs from column (t % 4) * 8.
+    const int lrow = t >> 2, lk = (t & 3) * 8;
+    const int64_t ll = r0 + lrow < nlos ? r0 + lrow : nlos - 1;
+    const float linv = inv_rms[lrow];
+    for (int k0 = 0; k0 < nin_pad; k0 += GK) {
+        f16x8_t xv;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int k = k0 + lk + e;
+            float x = 0.0f;
+            if (k < nchan) x = w[k] == 0.0f ? 0.0f : w[k] * Q[ll * nchan + k] * linv;
+            else if (k < 2 * nchan) {
+                const int j = k - nchan;
+                x = w[j] == 0.0f ? 0.0f : w[j] * U[ll * nchan + j] * linv;
+            }
+            xv[e] = (_Float16)x;
+        }
+        uint4 bv[2][2];
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+                bv[cb][s] = *reinterpret_cast<const uint4*>(
+                    W1 + (int64_t)(ncol + 32 * cb + r) * nin_pad + k0 + 16 * s + 8 * hsel);
+        __syncthreads();
+        *reinterpret_cast<f16x8_t*>(&sx[lrow][lk]) = xv;
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb) {
+                const uint4 a = *reinterpret_cast<const uint4*>(&sx[32 * rb + r][16 * s + 8 * hsel]);
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb)
+                    acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                        __builtin_bit_cast(f16x8_t, a), __builtin_bit_cast(f16x8_t, bv[cb][s]),
+                        acc[rb][cb], 0, 0, 0);
+            }
+        }
+    }
+    // h1 = relu(z1 + b1) as half into LDS.
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+        const int n = ncol + 32 * cb + r;
+        const float bn = b1[n];
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int m = 32 * rb + 8 * (v >> 2) + 4 * hsel + (v & 3);
+                const float z = __builtin_fmaf(1.0f, acc[rb][cb][v], bn);
+                sh[m][n] = (_Float16)(z < 0.0f ? 0.0f : z);
+                acc[rb][cb][v] = 0.0f;
+            }
+    }
+    __syncthreads();
+
+    // Layer 2 from the h1 tile.
+    for (int k0 = 0; k0 < FH; k0 += GK) {
+        uint4 bv[2][2];
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+                bv[cb][s] = *reinterpret_cast<const uint4*>(
+                    W2 + (int64_t)(ncol + 32 * cb + r) * FH + k0 + 16 * s + 8 * hsel);
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb) {
+                const uint4 a = *reinterpret_cast<const uint4*>(&sh[32 * rb + r][k0 + 16 * s + 8 * hsel]);
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb)
+                    acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                        __builtin_bit_cast(f16x8_t, a), __builtin_bit_cast(f16x8_t, bv[cb][s]),
+                        acc[rb][cb], 0, 0, 0);
+            }
+        }
+    }
+    // Head: h2 = relu(z2 + b2) rounded to half, dotted with the two rows of W3.
+    float p0[2][16], p1[2][16];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) p0[rb][v] = p1[rb][v] = 0.0f;
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+        const int n = ncol + 32 * cb + r;
+        const float bn = b2[n], w0 = (float)W3[n], w1 = (float)W3[FH + n];
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const float z = __builtin_fmaf(1.0f, acc[rb][cb][v], bn);
+                const float h = (float)(_Float16)(z < 0.0f ? 0.0f : z);
+                p0[rb][v] = __builtin_fmaf(h, w0, p0[rb][v]);
+                p1[rb][v] = __builtin_fmaf(h, w1, p1[rb][v]);
+            }
+    }
+    // Sum over the 32 lanes that share a row, then over the four waves.
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            float a = p0[rb][v], b = p1[rb][v];
+#pragma unroll
+            for (int off = 16; off > 0; off >>= 1) {
+                a += __shfl_xor(a, off, 64);
+                b += __shfl_xor(b, off, 64);
+            }
+            if (r == 0) {
+                const int m = 32 * rb + 8 * (v >> 2) + 4 * hsel + (v & 3);
+                part[wave][m][0] = a;
+                part[wave][m][1] = b;
+            }
+        }
+    __syncthreads();
+    if (t < FR && r0 + t < nlos) {
+        const float o0 = ((part[0][t][0] + part[1][t][0]) + (part[2][t][0] + part[3][t][0])) + b3[0];
+        const float o1 = ((part[0][t][1] + part[1][t][1]) + (part[2][t][1] + part[3][t][1])) + b3[1];
+        phi_hat[r0 + t] = o0 * phi_scale;
+        const float e = expf(-fabsf(o1));
+        score[r0 + t] = o1 >= 0.0f ? 1.0f / (1.0f + e) : e / (1.0f + e);
+    }
+}
+
 unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
 }  // namespace
@@ -350,5 +532,21 @@ hipError_t mlp_launch_weights16(const float* p, int64_t nW1, int64_t nb1, int64_
 hipError_t mlp_launch_mean(const float* x, int64_t n, float* out, hipStream_t s)
 {
     hipLaunchKernelGGL(mean_kernel, dim3(1), dim3(256), 0, s, x, n, out);
+    return hipGetLastError();
+}
+
+bool mlp_fused_supported(int h1, int h2, int nin_pad) { return h1 == FH && h2 == FH && nin_pad % GK == 0; }
+
+hipError_t mlp_launch_infer_fused(const float* Q, const float* U, int64_t nlos, int nchan,
+                                  const float* w, int nin_pad, const _Float16* W1, const float* b1,
+                                  const _Float16* W2, const float* b2, const _Float16* W3,
+                                  const float* b3, float phi_scale, float* phi_hat, float* score,
+                                  hipStream_t s)
+{
+    const int64_t blocks = (nlos + FR - 1) / FR;
+    if (blocks <= 0) return hipSuccess;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(infer_fused_kernel, dim3((unsigned)blocks), dim3(256), 0, s, Q, U, nlos, nchan,
+                       w, nin_pad, W1, b1, W2, b2, W3, b3, phi_scale, phi_hat, score);
     return hipGetLastError();
 }

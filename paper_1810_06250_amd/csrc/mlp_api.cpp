@@ -409,6 +409,15 @@ int rmsynth_mlp_infer(rmsynth_mlp_t m, const float* Q, const float* U, int64_t n
     if (!Q || !U || !phi_hat || !score) return rms_fail(RMSYNTH_EINVAL, "rmsynth_mlp_infer: NULL buffer");
     if (int rc = check_mlp_device(m)) return rc;
     hipStream_t s = (hipStream_t)stream;
+    if (mlp_fused_supported(m->h1, m->h2, m->nin_pad)) {
+        // One pass over the cube, no activation buffers.
+        hipError_t e = mlp_launch_infer_fused(Q, U, nlos, m->nchan, m->d_chw, m->nin_pad, W1h(m),
+                                              m->d_p + m->off_b1(), W2h(m), m->d_p + m->off_b2(),
+                                              W3h(m), m->d_p + m->off_b3(), m->phi_scale, phi_hat,
+                                              score, s);
+        if (e != hipSuccess) return rms_hip_fail(e, "rmsynth_mlp_infer");
+        return rms_ok();
+    }
     const int64_t chunk = std::min(round_up(nlos, 64), kInferChunk);
     if (int rc = ensure_rows(m, chunk, false)) return rc;
     for (int64_t l0 = 0; l0 < nlos; l0 += chunk) {

@@ -18,7 +18,8 @@
 // Im F of a LOS land in the same lane (accumulators v and v + 8).
 //
 // Workgroup: 256 threads, 128 LOS x 128 phi, 8 channels per K-step (one MFMA
-// K of 16), LDS double buffered (2 x 24 KB).  Waves 2 x 2, each 128 rows x
+// K of 16), LDS triple buffered (3 x 24 KB) so that the first fragments of a
+// K-step are read before the barrier that ends the previous one.  Waves 2 x 2, each 128 rows x
 // 64 columns = 4 x 2 blocks (128 accumulators per lane), so two workgroups
 // share a CU: while one waits on memory, a barrier or its output stores, the
 // other keeps the matrix cores busy.
@@ -63,7 +64,9 @@ __device__ __forceinline__ f32x16_t mfma16(uint4 a, uint4 b, f32x16_t c)
 
 // FAST: every K-step holds KC real channels (nchan % KC == 0) and, for
 // LOS-major input, rows are 16-byte aligned; the K-loop is then branch-free.
-template <int LAYOUT, bool FP16, bool FAST>
+// FLAGS: some channel has weight 0; its (zero) rotation then also clears
+// whatever the data hold there, NaN included.
+template <int LAYOUT, bool FP16, bool FAST, bool FLAGS>
 __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
     const float* __restrict__ Q, const float* __restrict__ U, int64_t nlos, int64_t ld,
     int nchan, const float2* __restrict__ base, const uint4* __restrict__ Thi,
@@ -71,9 +74,9 @@ __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
     float* __restrict__ Fq, float* __restrict__ Fu, float* __restrict__ Fabs,
     const float* __restrict__ los_scale)
 {
-    // Double-buffered A tiles (packed data) and T tiles (phase table).
-    __shared__ ABuf a0, a1;
-    __shared__ BBuf b0, b1;
+    // Triple-buffered A tiles (packed data) and T tiles (phase table).
+    __shared__ ABuf abuf[3];
+    __shared__ BBuf bbuf[3];
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const int64_t tm = tile / tiles_n;
     const int tn = (int)(tile - tm * tiles_n);
@@ -136,18 +139,19 @@ __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
         }
     };
 
-    // Channel i of the thread's 4: rotate, split.  A channel of weight 0
-    // (rotation exactly 0) contributes 0 whatever it holds, NaN included.
+    // Channel i of the thread's 4: rotate, split.
     uint32_t hi[4], lo[4];
     auto pack1 = [&](const Regs& R, int i) {
         const f32x4_t rr = R.rot[i >> 1];
         const float rc = (i & 1) ? rr.z : rr.x;
         const float rs = (i & 1) ? rr.w : rr.y;
-        const bool flagged = ((__float_as_uint(rc) | __float_as_uint(rs)) << 1) == 0u;
         float xr = __builtin_fmaf(R.q[i], rc, R.u[i] * rs);
         float yr = __builtin_fmaf(R.u[i], rc, -(R.q[i] * rs));
-        xr = flagged ? 0.0f : xr;
-        yr = flagged ? 0.0f : yr;
+        if (FLAGS) {
+            const bool flagged = ((__float_as_uint(rc) | __float_as_uint(rs)) << 1) == 0u;
+            xr = flagged ? 0.0f : xr;
+            yr = flagged ? 0.0f : yr;
+        }
         if (FP16) {
             xr *= lsc;
             yr *= lsc;
@@ -176,18 +180,26 @@ __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
             for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
 
     const int r = lane & 31, hsel = lane >> 5;
-    // One K-step of MFMAs (8 channels = one K of 16).  With P, the packing of
-    // the next K-step's A tile (registers P) is interleaved, one channel after
-    // each row block; the next row block's A fragments are read ahead.
-    auto mma = [&](const ABuf& cur, const BBuf& curb, const Regs* P) {
-        uint4 bh[2], bl[2];
+    // First fragments of a K-step (both B column blocks, A row block 0),
+    // read before the barrier that ends the previous K-step.
+    struct Frag {
+        uint4 bh[2], bl[2], ah, al;
+    };
+    auto load_frag = [&](Frag& F, const ABuf& a, const BBuf& b) {
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb) {
-            bh[cb] = curb.b_hi[hsel][64 * wc + 32 * cb + r];
-            bl[cb] = curb.b_lo[hsel][64 * wc + 32 * cb + r];
+            F.bh[cb] = b.b_hi[hsel][64 * wc + 32 * cb + r];
+            F.bl[cb] = b.b_lo[hsel][64 * wc + 32 * cb + r];
         }
-        uint4 ahn = cur.a_hi[hsel][128 * wr + r];
-        uint4 aln = cur.a_lo[hsel][128 * wr + r];
+        F.ah = a.a_hi[hsel][128 * wr + r];
+        F.al = a.a_lo[hsel][128 * wr + r];
+    };
+    // One K-step of MFMAs (8 channels = one K of 16) from buffer `cur` with
+    // first fragments F, the packing of a later K-step (registers P)
+    // interleaved one channel after each row block; the next row block's A
+    // fragments are read ahead.
+    auto mma = [&](const ABuf& cur, const Frag& F, const Regs& P) {
+        uint4 ahn = F.ah, aln = F.al;
 #pragma unroll
         for (int rb = 0; rb < 4; ++rb) {
             const uint4 ah = ahn, al = aln;
@@ -197,60 +209,66 @@ __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
             }
 #pragma unroll
             for (int cb = 0; cb < 2; ++cb) {
-                acc[rb][cb] = mfma16<FP16>(al, bh[cb], acc[rb][cb]);
-                acc[rb][cb] = mfma16<FP16>(ah, bl[cb], acc[rb][cb]);
-                acc[rb][cb] = mfma16<FP16>(ah, bh[cb], acc[rb][cb]);
+                acc[rb][cb] = mfma16<FP16>(al, F.bh[cb], acc[rb][cb]);
+                acc[rb][cb] = mfma16<FP16>(ah, F.bl[cb], acc[rb][cb]);
+                acc[rb][cb] = mfma16<FP16>(ah, F.bh[cb], acc[rb][cb]);
             }
-            if (P) pack1(*P, rb);
+            pack1(P, rb);
         }
     };
 
-    // Make the next buffers visible to all waves: this wave's LDS writes
-    // done, then the barrier.  Written out instead of __syncthreads(), whose
-    // release fence would also wait for the prefetch loads still in flight
-    // (they only fill registers).
+    // Make the buffers written in this K-step visible to all waves: this
+    // wave's LDS reads and writes done, then the barrier.  Written out
+    // instead of __syncthreads(), whose release fence would also wait for
+    // the prefetch loads still in flight (they only fill registers).
     auto sync_next = [&]() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); };
 
-    // Prologue: K-step 0 packed into (a0, b0), K-step 1 loading into R1.
+    // Three LDS buffers rotate: K-step k is contracted from buffer k % 3
+    // while K-step k + 2 is packed into buffer (k + 2) % 3 (last read in step
+    // k - 1, before the previous barrier) and the first fragments of k + 1
+    // are read from buffer (k + 1) % 3 (complete since the previous barrier).
+    // Two register sets alternate: step k packs R[k % 2] (K-step k + 2) and
+    // loads K-step k + 3 into R[(k + 1) % 2].  Load indices past the end are
+    // clamped to the last K-step (loaded, never stored).
+    Frag F;
+    int bc = 0;  // buffer of K-step k; (bc + 1) % 3 and (bc + 2) % 3 follow
+    auto step = [&](Regs& Rp, Regs& Rl, int k) {
+        const int bf = bc == 2 ? 0 : bc + 1;
+        const int bn = bf == 2 ? 0 : bf + 1;
+        gload(Rl, k + 3 < nk ? k + 3 : nk - 1);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(abuf[bc], F, Rp);
+        if (k + 2 < nk) {
+            store_a(abuf[bn]);
+            store_t(bbuf[bn], Rp);
+        }
+        if (k + 1 < nk) load_frag(F, abuf[bf], bbuf[bf]);
+        sync_next();
+        bc = bf;
+    };
+
+    // Prologue: K-steps 0 and 1 packed into buffers 0 and 1, K-step 2 loading
+    // into R0, the first fragments of K-step 0 read after the barrier.
     gload(R0, 0);
     gload(R1, nk > 1 ? 1 : 0);
 #pragma unroll
     for (int i = 0; i < 4; ++i) pack1(R0, i);
-    store_a(a0);
-    store_t(b0, R0);
+    store_a(abuf[0]);
+    store_t(bbuf[0], R0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) pack1(R1, i);
+    store_a(abuf[1]);
+    store_t(bbuf[1], R1);
+    gload(R0, nk > 2 ? 2 : nk - 1);
     sync_next();
+    load_frag(F, abuf[0], bbuf[0]);
 
-    // Pairs of K-steps: contract ks from buffers 0 while packing ks + 1 (R1)
-    // into buffers 1 and loading ks + 2 into R0; then contract ks + 1 from
-    // buffers 1 while packing ks + 2 (R0) into buffers 0 and loading ks + 3
-    // into R1.  The loads are issued at the top of a step (the scheduling
-    // barrier keeps them there); a prefetch index past the end is clamped to
-    // the last K-step (loaded, never used).
-    int ks = 0;
-    for (; ks + 2 < nk; ks += 2) {
-        gload(R0, ks + 2);
-        __builtin_amdgcn_sched_barrier(0);
-        mma(a0, b0, &R1);
-        store_a(a1);
-        store_t(b1, R1);
-        sync_next();
-
-        gload(R1, ks + 3 < nk ? ks + 3 : nk - 1);
-        __builtin_amdgcn_sched_barrier(0);
-        mma(a1, b1, &R0);
-        store_a(a0);
-        store_t(b0, R0);
-        sync_next();
+    int k = 0;
+    for (; k + 1 < nk; k += 2) {
+        step(R0, R1, k);
+        step(R1, R0, k + 1);
     }
-    if (ks + 1 < nk) {  // two K-steps left: ks in buffers 0, ks + 1 in R1
-        mma(a0, b0, &R1);
-        store_a(a1);
-        store_t(b1, R1);
-        sync_next();
-        mma(a1, b1, nullptr);
-    } else {            // one K-step left, in buffers 0
-        mma(a0, b0, nullptr);
-    }
+    if (k < nk) step(R0, R1, k);
 
     // Epilogue: block rb holds LOS 64 wr + 16 rb + i; Re F in v < 8, Im F in v + 8.
     // Tiles wholly inside the output (the common case) store without checks.
@@ -301,13 +319,13 @@ __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
 }
 
 // Plan-time tables (FP64 argument reduction, FP32 sin/cos):
-//   base[t][j] = K w_j (cos, sin)(2 pi (phi_0 + 256 t dphi) b_j)   (K of eq. (13) folded in)
+//   base[t][j] = K w_j (cos, sin)(2 pi (phi_0 + NT t dphi) b_j)   (K of eq. (13) folded in)
 //   T[j][m]    = (cos, sin)(2 pi m dphi b_j), stored per 4-channel quad and split.
 __global__ void factor_tables_kernel(const double* __restrict__ bj, const float* __restrict__ wj,
                                      int nchan_pad, int ftiles, double phi0, double dphi, double K,
                                      float2* __restrict__ base, uint4* __restrict__ bf_hi,
                                      uint4* __restrict__ bf_lo, uint4* __restrict__ hf_hi,
-                                     uint4* __restrict__ hf_lo, float4* __restrict__ f32)
+                                     uint4* __restrict__ hf_lo)
 {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nT = (int64_t)(nchan_pad / 4) * NT;
@@ -326,8 +344,6 @@ __global__ void factor_tables_kernel(const double* __restrict__ bj, const float*
         bf_lo[idx] = make_uint4(bl[0], bl[1], bl[2], bl[3]);
         hf_hi[idx] = make_uint4(hh[0], hh[1], hh[2], hh[3]);
         hf_lo[idx] = make_uint4(hl[0], hl[1], hl[2], hl[3]);
-        f32[(int64_t)(2 * quad) * NT + m] = make_float4(cs[0], sn[0], cs[1], sn[1]);
-        f32[(int64_t)(2 * quad + 1) * NT + m] = make_float4(cs[2], sn[2], cs[3], sn[3]);
     }
     const int64_t nB = (int64_t)ftiles * nchan_pad;
     if (idx < nB) {
@@ -396,17 +412,24 @@ hipError_t launch_t(const rmsynth_plan_s& p, const ExecArgs& a)
     const uint4* Thi = FP16 ? p.d_Thf[0] : p.d_Tbf[0];
     const uint4* Tlo = FP16 ? p.d_Thf[1] : p.d_Tbf[1];
     const bool full_k = p.nchan % KC == 0;
-#define RMS_LAUNCH(L, F)                                                                       \
-    hipLaunchKernelGGL((synth_factored_kernel<L, FP16, F>), dim3((unsigned)blocks), dim3(256), 0, \
-                       a.stream, a.Q, a.U, a.nlos, a.ld, p.nchan, p.d_base, Thi, Tlo,            \
+    const bool fast = full_k && (a.layout != RMSYNTH_LOS_MAJOR || a.vec4);
+#define RMS_LAUNCH(L, F, G)                                                                        \
+    hipLaunchKernelGGL((synth_factored_kernel<L, FP16, F, G>), dim3((unsigned)blocks), dim3(256), 0, \
+                       a.stream, a.Q, a.U, a.nlos, a.ld, p.nchan, p.d_base, Thi, Tlo,               \
                        p.nchan_pad, nk, p.nphi, tiles_n, a.Fq, a.Fu, a.Fabs, a.los_scale)
+#define RMS_LAUNCH_G(L, F)                         \
+    do {                                           \
+        if (p.any_flagged) RMS_LAUNCH(L, F, true); \
+        else RMS_LAUNCH(L, F, false);              \
+    } while (0)
     if (a.layout == RMSYNTH_LOS_MAJOR) {
-        if (full_k && a.vec4) RMS_LAUNCH(RMSYNTH_LOS_MAJOR, true);
-        else RMS_LAUNCH(RMSYNTH_LOS_MAJOR, false);
+        if (fast) RMS_LAUNCH_G(RMSYNTH_LOS_MAJOR, true);
+        else RMS_LAUNCH_G(RMSYNTH_LOS_MAJOR, false);
     } else {
-        if (full_k) RMS_LAUNCH(RMSYNTH_FREQ_MAJOR, true);
-        else RMS_LAUNCH(RMSYNTH_FREQ_MAJOR, false);
+        if (fast) RMS_LAUNCH_G(RMSYNTH_FREQ_MAJOR, true);
+        else RMS_LAUNCH_G(RMSYNTH_FREQ_MAJOR, false);
     }
+#undef RMS_LAUNCH_G
 #undef RMS_LAUNCH
     return hipGetLastError();
 }
@@ -438,6 +461,6 @@ hipError_t launch_factor_tables(const rmsynth_plan_s& p, hipStream_t stream)
     const int64_t n = nT > nB ? nT : nB;
     hipLaunchKernelGGL(factor_tables_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream,
                        p.d_b, p.d_w, p.nchan_pad, p.ftiles, p.phi0, p.dphi, p.K, p.d_base, p.d_Tbf[0],
-                       p.d_Tbf[1], p.d_Thf[0], p.d_Thf[1], p.d_Tf32);
+                       p.d_Tbf[1], p.d_Thf[0], p.d_Thf[1]);
     return hipGetLastError();
 }

@@ -132,9 +132,13 @@ WORKLOADS = {
     "c4": Workload("c4", 2048, 2048, 110.0, 190.0, 1024, 0, -1000.0, 1000.0, 0.5, 1e-4,
                    FREQ_MAJOR, 0.002, 0, 0, phi0=(-800.0, 800.0), seed=1004,
                    note="large low-frequency cube, FP16 split vs FP32"),
-    # Gating inference cube: 2048^2 LOS, 288 channels 800-1088 MHz, phi -300..300 step 0.5.
+    # Gating inference cube: 2048^2 LOS, 288 channels 800-1088 MHz, phi -300..300 step 0.5;
+    # 1 % of LOS with 1-2 thin components, 0.5 % with a slab, peak SNR 3-50 against the
+    # noise of F (sigma_F = 1e-3 / sqrt(288) for 288 unit-weight channels).
     "c5": Workload("c5", 2048, 2048, 800.0, 1088.0, 288, 0, -300.0, 300.0, 0.5, 1e-3,
-                   LOS_MAJOR, 0.005, 0.005, 0.005, phi0=(-300.0, 300.0), slab_W=(10.0, 100.0),
+                   LOS_MAJOR, 0.005, 0.005, 0.005,
+                   P0=(3e-3 / np.sqrt(288.0), 50e-3 / np.sqrt(288.0)),
+                   phi0=(-300.0, 300.0), slab_W=(10.0, 100.0),
                    seed=1005, note="learned gating inference cube"),
 }
 
