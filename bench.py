@@ -38,7 +38,7 @@ METRIC = "LOS·chan·φ Gsamples/s + % MFMA peak, split-BF16 vs FP32 at ≤1e-5 
 # taken on).  A changed kernel source reports null until counters are retaken.
 KERNEL_SRC = os.path.join(ROOT, "paper_1810_06250_amd", "csrc", "synth_factored.hip")
 TRAFFIC = {
-    ("c3", "bf16x3", "9f214bb72bf5960f"): 2.0 * 6670351 * 1024 + 1.0 * 25248864 * 1024,
+    ("c3", "bf16x3", "145e04a038f0c7b4"): 2.0 * 1763120 * 1024 + 1.0 * 16726100 * 1024,
 }
 
 

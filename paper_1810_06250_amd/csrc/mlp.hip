@@ -272,17 +272,21 @@ __global__ __launch_bounds__(256) void mean_kernel(const float* __restrict__ x, 
 }
 
 // ----------------------------------------------------------------- fused inference
-// One workgroup per 64 LOS, hidden widths 256 and 256: per-LOS rms, then
-// layer 1 with the input tile normalised and rounded to half on its way into
-// LDS (the same FP32 expression as input_kernel), layer 2 from the half h1
-// tile in LDS, and the head, without any activation leaving the CU.  Weights
-// are read from L2 straight into the B-operand registers.  z1 and z2 are
-// bitwise those of the unfused GEMMs (same MFMA k order); the head sums its
-// 256 products in another order.
+// One workgroup per 64 LOS, hidden widths 256 and 256.  Thread t loads row
+// t / 4, inputs (t % 4) * 8 .. + 7 of every 32-wide K-chunk, one chunk ahead
+// of its use.  Pass 1 over the row accumulates sum (w Q)^2 + (w U)^2 (the
+// four threads of a row combine theirs by shuffles, a fixed order); pass 2
+// streams the same chunks again (mostly from L2/MALL), normalises and rounds
+// them to half on their way into LDS, and feeds layer 1; layer 2 reads the
+// half h1 tile from LDS; the head reduces over lanes and waves.  Weights are
+// read from L2 straight into the B-operand registers.  No activation leaves
+// the CU.  VEC: nchan % 32 == 0 and 16-byte aligned rows, so every chunk lies
+// in Q or in U and loads as two float4.
 constexpr int FR = 64;                 // LOS per workgroup
 constexpr int FH = 256;                // hidden width
 constexpr int FHS = FH + 8;            // LDS row stride of h1 (halves)
 
+template <bool VEC>
 __global__ __launch_bounds__(256, 2) void infer_fused_kernel(
     const float* __restrict__ Q, const float* __restrict__ U, int64_t nlos, int nchan,
     const float* __restrict__ w, int nin_pad, const _Float16* __restrict__ W1,
@@ -290,32 +294,72 @@ __global__ __launch_bounds__(256, 2) void infer_fused_kernel(
     const _Float16* __restrict__ W3, const float* __restrict__ b3, float phi_scale,
     float* __restrict__ phi_hat, float* __restrict__ score)
 {
-    __shared__ float inv_rms[FR];
-    __shared__ _Float16 sx[FR][GRS];     // one K-step of the input tile
+    __shared__ _Float16 sx[2][FR][GRS];  // K-chunks of the input tile, double buffered
     __shared__ _Float16 sh[FR][FHS];     // h1
     __shared__ float part[4][FR][2];     // head partial sums per wave
     const int t = threadIdx.x, lane = t & 63;
     const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
     const int64_t r0 = (int64_t)blockIdx.x * FR;
+    const int lrow = t >> 2, lk = (t & 3) * 8;
+    // Rows past the end read the last LOS (in bounds); their outputs are never stored.
+    const int64_t ll = r0 + lrow < nlos ? r0 + lrow : nlos - 1;
+    const float* qrow = Q + ll * nchan;
+    const float* urow = U + ll * nchan;
+    const int nin = 2 * nchan;
 
-    // rms of each row (rows past the end read the last LOS; never stored).
-    for (int i = 0; i < FR / 4; ++i) {
-        const int row = wave * (FR / 4) + i;
-        const int64_t l = r0 + row < nlos ? r0 + row : nlos - 1;
-        const float* q = Q + l * nchan;
-        const float* u = U + l * nchan;
-        float ss = 0.0f;
-        for (int j = lane; j < nchan; j += 64) {
-            const float a = w[j] == 0.0f ? 0.0f : w[j] * q[j];
-            const float c = w[j] == 0.0f ? 0.0f : w[j] * u[j];
-            ss = __builtin_fmaf(a, a, __builtin_fmaf(c, c, ss));
-        }
+    // The thread's 8 inputs of chunk k0 (raw data) and their channel weights.
+    auto load = [&](int k0, float (&v)[8], float (&wv)[8]) {
+        if (VEC) {
+            const int k = k0 + lk;
+            if (k0 < nin) {
+                const float* src = k0 < nchan ? qrow + k : urow + (k - nchan);
+                const float* ws = w + (k0 < nchan ? k : k - nchan);
+                const float4 a = *reinterpret_cast<const float4*>(src);
+                const float4 b = *reinterpret_cast<const float4*>(src + 4);
+                const float4 c = *reinterpret_cast<const float4*>(ws);
+                const float4 d = *reinterpret_cast<const float4*>(ws + 4);
+                v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+                v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+                wv[0] = c.x; wv[1] = c.y; wv[2] = c.z; wv[3] = c.w;
+                wv[4] = d.x; wv[5] = d.y; wv[6] = d.z; wv[7] = d.w;
+            } else {
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off, 64);
-        if (lane == 0)
-            inv_rms[row] = ss > 0.0f ? 1.0f / sqrtf(ss / (float)(2 * nchan)) : (ss == 0.0f ? 0.0f : ss);
+                for (int e = 0; e < 8; ++e) v[e] = wv[e] = 0.0f;
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int k = k0 + lk + e;
+                const int j = k < nchan ? k : k - nchan;
+                const bool ok = k < nin;
+                v[e] = ok ? (k < nchan ? qrow[j] : urow[j]) : 0.0f;
+                wv[e] = ok ? w[j] : 0.0f;
+            }
+        }
+    };
+
+    // Pass 1: sum of squares of the weighted inputs of the row.
+    float ss = 0.0f;
+    {
+        float v[8], wv[8], vn[8], wn[8];
+        load(0, v, wv);
+        for (int k0 = 0; k0 < nin_pad; k0 += GK) {
+            if (k0 + GK < nin_pad) load(k0 + GK, vn, wn);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const float a = wv[e] == 0.0f ? 0.0f : wv[e] * v[e];
+                ss = __builtin_fmaf(a, a, ss);
+            }
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                v[e] = vn[e];
+                wv[e] = wn[e];
+            }
+        }
     }
-    __syncthreads();
+    ss += __shfl_xor(ss, 1, 64);
+    ss += __shfl_xor(ss, 2, 64);
+    const float inv = ss > 0.0f ? 1.0f / sqrtf(ss / (float)nin) : (ss == 0.0f ? 0.0f : ss);
 
     const int r = lane & 31, hsel = lane >> 5;
     const int ncol = 64 * wave;              // this wave's 64 hidden units
@@ -327,44 +371,56 @@ __global__ __launch_bounds__(256, 2) void infer_fused_kernel(
 #pragma unroll
             for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
 
-    // Layer 1.  Loader: row t / 4, 8 consecutive inputs from column (t % 4) * 8.
-    const int lrow = t >> 2, lk = (t & 3) * 8;
-    const int64_t ll = r0 + lrow < nlos ? r0 + lrow : nlos - 1;
-    const float linv = inv_rms[lrow];
-    for (int k0 = 0; k0 < nin_pad; k0 += GK) {
-        f16x8_t xv;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int k = k0 + lk + e;
-            float x = 0.0f;
-            if (k < nchan) x = w[k] == 0.0f ? 0.0f : w[k] * Q[ll * nchan + k] * linv;
-            else if (k < 2 * nchan) {
-                const int j = k - nchan;
-                x = w[j] == 0.0f ? 0.0f : w[j] * U[ll * nchan + j] * linv;
-            }
-            xv[e] = (_Float16)x;
-        }
-        uint4 bv[2][2];
+    // Pass 2: layer 1, chunk k0 contracted from sx[buf] while chunk k0 + 32 loads.
+    auto wfrag = [&](const _Float16* W, int ld, int k0, uint4 (&bv)[2][2]) {
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
             for (int s = 0; s < 2; ++s)
                 bv[cb][s] = *reinterpret_cast<const uint4*>(
-                    W1 + (int64_t)(ncol + 32 * cb + r) * nin_pad + k0 + 16 * s + 8 * hsel);
-        __syncthreads();
-        *reinterpret_cast<f16x8_t*>(&sx[lrow][lk]) = xv;
-        __syncthreads();
+                    W + (int64_t)(ncol + 32 * cb + r) * ld + k0 + 16 * s + 8 * hsel);
+    };
+    auto stage = [&](int buf, const float (&v)[8], const float (&wv)[8]) {
+        f16x8_t xv;
 #pragma unroll
-        for (int s = 0; s < 2; ++s) {
+        for (int e = 0; e < 8; ++e) xv[e] = (_Float16)(wv[e] == 0.0f ? 0.0f : wv[e] * v[e] * inv);
+        *reinterpret_cast<f16x8_t*>(&sx[buf][lrow][lk]) = xv;
+    };
+    {
+        float v[8], wv[8];
+        uint4 bv[2][2], bn[2][2];
+        load(0, v, wv);
+        stage(0, v, wv);
+        wfrag(W1, nin_pad, 0, bv);
+        __syncthreads();
+        int buf = 0;
+        for (int k0 = 0; k0 < nin_pad; k0 += GK) {
+            const bool more = k0 + GK < nin_pad;
+            if (more) {
+                load(k0 + GK, v, wv);
+                wfrag(W1, nin_pad, k0 + GK, bn);
+            }
 #pragma unroll
-            for (int rb = 0; rb < 2; ++rb) {
-                const uint4 a = *reinterpret_cast<const uint4*>(&sx[32 * rb + r][16 * s + 8 * hsel]);
+            for (int s = 0; s < 2; ++s) {
+#pragma unroll
+                for (int rb = 0; rb < 2; ++rb) {
+                    const uint4 a = *reinterpret_cast<const uint4*>(&sx[buf][32 * rb + r][16 * s + 8 * hsel]);
+#pragma unroll
+                    for (int cb = 0; cb < 2; ++cb)
+                        acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                            __builtin_bit_cast(f16x8_t, a), __builtin_bit_cast(f16x8_t, bv[cb][s]),
+                            acc[rb][cb], 0, 0, 0);
+                }
+            }
+            if (more) {
+                stage(buf ^ 1, v, wv);
 #pragma unroll
                 for (int cb = 0; cb < 2; ++cb)
-                    acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
-                        __builtin_bit_cast(f16x8_t, a), __builtin_bit_cast(f16x8_t, bv[cb][s]),
-                        acc[rb][cb], 0, 0, 0);
+#pragma unroll
+                    for (int s = 0; s < 2; ++s) bv[cb][s] = bn[cb][s];
             }
+            __syncthreads();
+            buf ^= 1;
         }
     }
     // h1 = relu(z1 + b1) as half into LDS.
@@ -384,25 +440,30 @@ __global__ __launch_bounds__(256, 2) void infer_fused_kernel(
     }
     __syncthreads();
 
-    // Layer 2 from the h1 tile.
-    for (int k0 = 0; k0 < FH; k0 += GK) {
-        uint4 bv[2][2];
+    // Layer 2 from the h1 tile, W2 fragments one chunk ahead.
+    {
+        uint4 bv[2][2], bn[2][2];
+        wfrag(W2, FH, 0, bv);
+        for (int k0 = 0; k0 < FH; k0 += GK) {
+            const bool more = k0 + GK < FH;
+            if (more) wfrag(W2, FH, k0 + GK, bn);
 #pragma unroll
-        for (int cb = 0; cb < 2; ++cb)
+            for (int s = 0; s < 2; ++s) {
 #pragma unroll
-            for (int s = 0; s < 2; ++s)
-                bv[cb][s] = *reinterpret_cast<const uint4*>(
-                    W2 + (int64_t)(ncol + 32 * cb + r) * FH + k0 + 16 * s + 8 * hsel);
+                for (int rb = 0; rb < 2; ++rb) {
+                    const uint4 a = *reinterpret_cast<const uint4*>(&sh[32 * rb + r][k0 + 16 * s + 8 * hsel]);
 #pragma unroll
-        for (int s = 0; s < 2; ++s) {
-#pragma unroll
-            for (int rb = 0; rb < 2; ++rb) {
-                const uint4 a = *reinterpret_cast<const uint4*>(&sh[32 * rb + r][k0 + 16 * s + 8 * hsel]);
+                    for (int cb = 0; cb < 2; ++cb)
+                        acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                            __builtin_bit_cast(f16x8_t, a), __builtin_bit_cast(f16x8_t, bv[cb][s]),
+                            acc[rb][cb], 0, 0, 0);
+                }
+            }
+            if (more) {
 #pragma unroll
                 for (int cb = 0; cb < 2; ++cb)
-                    acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
-                        __builtin_bit_cast(f16x8_t, a), __builtin_bit_cast(f16x8_t, bv[cb][s]),
-                        acc[rb][cb], 0, 0, 0);
+#pragma unroll
+                    for (int s = 0; s < 2; ++s) bv[cb][s] = bn[cb][s];
             }
         }
     }
@@ -546,7 +607,13 @@ hipError_t mlp_launch_infer_fused(const float* Q, const float* U, int64_t nlos, 
     const int64_t blocks = (nlos + FR - 1) / FR;
     if (blocks <= 0) return hipSuccess;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(infer_fused_kernel, dim3((unsigned)blocks), dim3(256), 0, s, Q, U, nlos, nchan,
-                       w, nin_pad, W1, b1, W2, b2, W3, b3, phi_scale, phi_hat, score);
+    const bool vec = nchan % GK == 0 && (uintptr_t)Q % 16 == 0 && (uintptr_t)U % 16 == 0 &&
+                     (uintptr_t)w % 16 == 0;
+    if (vec)
+        hipLaunchKernelGGL(infer_fused_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, s, Q, U, nlos,
+                           nchan, w, nin_pad, W1, b1, W2, b2, W3, b3, phi_scale, phi_hat, score);
+    else
+        hipLaunchKernelGGL(infer_fused_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, s, Q, U,
+                           nlos, nchan, w, nin_pad, W1, b1, W2, b2, W3, b3, phi_scale, phi_hat, score);
     return hipGetLastError();
 }

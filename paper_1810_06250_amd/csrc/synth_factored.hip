@@ -238,11 +238,17 @@ __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
         gload(Rl, k + 3 < nk ? k + 3 : nk - 1);
         __builtin_amdgcn_sched_barrier(0);
         mma(abuf[bc], F, Rp);
-        if (k + 2 < nk) {
-            store_a(abuf[bn]);
-            store_t(bbuf[bn], Rp);
+        // Unconditional: past the last K-step these write a buffer nobody
+        // reads again and read one that is not used (both in bounds), which
+        // keeps the step one straight-line region for the scheduler.
+        store_a(abuf[bn]);
+        store_t(bbuf[bn], Rp);
+        load_frag(F, abuf[bf], bbuf[bf]);
+#pragma unroll
+        for (int i = 0; i < 24; ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);
         }
-        if (k + 1 < nk) load_frag(F, abuf[bf], bbuf[bf]);
         sync_next();
         bc = bf;
     };

@@ -266,6 +266,12 @@ def test_c3_full_size_sampled():
     _full_size("c3", ["bf16x3", "fp32", "fp16x3"], 4096)
 
 
+def test_c4_full_size_sampled():
+    """2048^2 LOS, 1024 channels 110-190 MHz (phase arguments up to ~1e4 rad),
+    4001 phi, frequency-major: the FP16 split against FP32 (168 GB resident)."""
+    _full_size("c4", ["fp16x3", "fp32", "bf16x3"], 2048)
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
 @pytest.mark.parametrize("layout", [LOS_MAJOR, FREQ_MAJOR], ids=["los", "freq"])
 def test_nonuniform_phi_grid(prec, layout):
