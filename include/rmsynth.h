@@ -139,6 +139,28 @@ int rmsynth_execute(rmsynth_plan_t plan, const float* Q, const float* U, int64_t
                     void* workspace, size_t workspace_bytes, void* stream);
 
 /*
+ * rmsynth_execute_peaks -- rmsynth_execute followed by rmsynth_peaks on its
+ * outputs, in one call: arguments as there (Fq, Fu are written as by
+ * rmsynth_execute; idx, phi_pk, amp, q_pk, u_pk as by rmsynth_peaks, idx
+ * required, the others may be NULL).  With a split precision on a uniform phi
+ * grid the transform kernels reduce |F|^2 per (LOS, phi tile) while the tile
+ * is still in registers and a small kernel merges the tiles, so the outputs are
+ * not read back; the results are identical to the two separate calls.
+ *   workspace: at least rmsynth_execute_peaks_workspace_size() bytes (the
+ *   FP16 split's per-LOS scales, then 8 bytes per LOS and phi tile of 128).
+ * Errors as rmsynth_execute.
+ */
+int rmsynth_execute_peaks(rmsynth_plan_t plan, const float* Q, const float* U, int64_t nlos,
+                          int32_t layout, int32_t precision, float* Fq, float* Fu, float* Fabs,
+                          int32_t* idx, float* phi_pk, float* amp, float* q_pk, float* u_pk,
+                          void* workspace, size_t workspace_bytes, void* stream);
+
+/* rmsynth_execute_peaks_workspace_size -- device workspace rmsynth_execute_peaks
+ * needs for nlos LOS in the given layout and precision. */
+int rmsynth_execute_peaks_workspace_size(rmsynth_plan_t plan, int64_t nlos, int32_t layout,
+                                         int32_t precision, size_t* bytes);
+
+/*
  * rmsynth_peaks -- per-LOS peak of |F| (the Faraday depth phi_peak where |F|
  * is largest, Section 2.2 after eq. (14)).
  *   Fq, Fu   [nlos][nphi] device float (as written by rmsynth_execute).

@@ -216,30 +216,37 @@ int rmsynth_rmsf(rmsynth_plan_t p, float* R_re, float* R_im, void* stream)
     return rms_ok();
 }
 
-int rmsynth_execute(rmsynth_plan_t p, const float* Q, const float* U, int64_t nlos, int32_t layout,
-                    int32_t precision, float* Fq, float* Fu, float* Fabs, void* workspace,
-                    size_t workspace_bytes, void* stream)
-{
-    if (!p) return rms_fail(RMSYNTH_EINVAL, "rmsynth_execute: plan is NULL");
-    if (nlos < 0) return rms_fail(RMSYNTH_EINVAL, "rmsynth_execute: nlos=%lld", (long long)nlos);
-    if (layout != RMSYNTH_LOS_MAJOR && layout != RMSYNTH_FREQ_MAJOR)
-        return rms_fail(RMSYNTH_EINVAL, "rmsynth_execute: layout=%d", layout);
-    if (precision < RMSYNTH_FP32 || precision > RMSYNTH_SPLIT_FP16)
-        return rms_fail(RMSYNTH_EINVAL, "rmsynth_execute: precision=%d", precision);
-    if (nlos == 0) return rms_ok();
-    if (!Q || !U || !Fq || !Fu) return rms_fail(RMSYNTH_EINVAL, "rmsynth_execute: NULL buffer");
-    if (precision == RMSYNTH_SPLIT_FP16) {
-        if (!p->uniform)
-            return rms_fail(RMSYNTH_EUNSUPPORTED,
-                        "rmsynth_execute: the FP16 split needs a uniform phi grid");
-        const size_t need = (size_t)round_up(nlos * 4, 256);
-        if (!workspace || workspace_bytes < need)
-            return rms_fail(RMSYNTH_EWORKSPACE, "rmsynth_execute: FP16 split needs %zu workspace bytes, got %zu",
-                        need, workspace ? workspace_bytes : (size_t)0);
-    }
-    if (int rc = check_device(p)) return rc;
+}  // extern "C"
 
-    // Launch in LOS batches so that one grid stays below kMaxBlocks.
+namespace {
+
+size_t scale_bytes(int64_t nlos) { return (size_t)round_up(std::max<int64_t>(nlos, 1) * 4, 256); }
+
+bool fused_peaks(const rmsynth_plan_s* p, int32_t precision)
+{
+    return precision != RMSYNTH_FP32 && p->uniform;
+}
+
+int check_execute_args(const rmsynth_plan_s* p, int64_t nlos, int32_t layout, int32_t precision,
+                       const char* who)
+{
+    if (!p) return rms_fail(RMSYNTH_EINVAL, "%s: plan is NULL", who);
+    if (nlos < 0) return rms_fail(RMSYNTH_EINVAL, "%s: nlos=%lld", who, (long long)nlos);
+    if (layout != RMSYNTH_LOS_MAJOR && layout != RMSYNTH_FREQ_MAJOR)
+        return rms_fail(RMSYNTH_EINVAL, "%s: layout=%d", who, layout);
+    if (precision < RMSYNTH_FP32 || precision > RMSYNTH_SPLIT_FP16)
+        return rms_fail(RMSYNTH_EINVAL, "%s: precision=%d", who, precision);
+    if (precision == RMSYNTH_SPLIT_FP16 && !p->uniform)
+        return rms_fail(RMSYNTH_EUNSUPPORTED, "%s: the FP16 split needs a uniform phi grid", who);
+    return RMSYNTH_OK;
+}
+
+// The transform in LOS batches (one grid stays below kMaxBlocks); with parts,
+// the factored kernels also write their per-tile peaks.
+int run_execute(const rmsynth_plan_s* p, const float* Q, const float* U, int64_t nlos, int32_t layout,
+                int32_t precision, float* Fq, float* Fu, float* Fabs, float* scales, PeakPart* parts,
+                hipStream_t stream, const char* who)
+{
     const int64_t tiles_n = (p->nphi + 127) / 128;
     const int64_t max_los = std::max<int64_t>(128, kMaxBlocks / tiles_n * 64);
     for (int64_t l0 = 0; l0 < nlos;) {
@@ -261,19 +268,92 @@ int rmsynth_execute(rmsynth_plan_t p, const float* Q, const float* U, int64_t nl
         a.Fq = Fq + l0 * p->nphi;
         a.Fu = Fu + l0 * p->nphi;
         a.Fabs = Fabs ? Fabs + l0 * p->nphi : nullptr;
-        a.los_scale = precision == RMSYNTH_SPLIT_FP16 ? static_cast<float*>(workspace) + l0 : nullptr;
-        a.stream = (hipStream_t)stream;
+        a.los_scale = precision == RMSYNTH_SPLIT_FP16 ? scales + l0 : nullptr;
+        a.peak_part = parts ? parts + l0 * factored_peak_parts(*p) : nullptr;
+        a.stream = stream;
         if (precision == RMSYNTH_SPLIT_FP16) {
             hipError_t e = launch_los_scale(*p, a);
-            if (e != hipSuccess) return rms_hip_fail(e, "rmsynth_execute scale launch");
+            if (e != hipSuccess) return rms_hip_fail(e, who);
         }
         hipError_t e;
         if (precision == RMSYNTH_FP32) e = launch_synth_fp32(*p, a);
         else if (p->uniform) e = launch_synth_factored(*p, a, precision);
         else e = launch_synth_split(*p, a, precision);
-        if (e != hipSuccess) return rms_hip_fail(e, "rmsynth_execute launch");
+        if (e != hipSuccess) return rms_hip_fail(e, who);
         l0 += n;
     }
+    return RMSYNTH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rmsynth_execute(rmsynth_plan_t p, const float* Q, const float* U, int64_t nlos, int32_t layout,
+                    int32_t precision, float* Fq, float* Fu, float* Fabs, void* workspace,
+                    size_t workspace_bytes, void* stream)
+{
+    if (int rc = check_execute_args(p, nlos, layout, precision, "rmsynth_execute")) return rc;
+    if (nlos == 0) return rms_ok();
+    if (!Q || !U || !Fq || !Fu) return rms_fail(RMSYNTH_EINVAL, "rmsynth_execute: NULL buffer");
+    if (precision == RMSYNTH_SPLIT_FP16) {
+        const size_t need = (size_t)round_up(nlos * 4, 256);
+        if (!workspace || workspace_bytes < need)
+            return rms_fail(RMSYNTH_EWORKSPACE, "rmsynth_execute: FP16 split needs %zu workspace bytes, got %zu",
+                            need, workspace ? workspace_bytes : (size_t)0);
+    }
+    if (int rc = check_device(p)) return rc;
+    if (int rc = run_execute(p, Q, U, nlos, layout, precision, Fq, Fu, Fabs,
+                             static_cast<float*>(workspace), nullptr, (hipStream_t)stream,
+                             "rmsynth_execute launch"))
+        return rc;
+    return rms_ok();
+}
+
+int rmsynth_execute_peaks_workspace_size(rmsynth_plan_t p, int64_t nlos, int32_t layout,
+                                         int32_t precision, size_t* bytes)
+{
+    if (!bytes) return rms_fail(RMSYNTH_EINVAL, "rmsynth_execute_peaks_workspace_size: bytes is NULL");
+    if (int rc = check_execute_args(p, nlos, layout, precision, "rmsynth_execute_peaks_workspace_size"))
+        return rc;
+    size_t b = precision == RMSYNTH_SPLIT_FP16 ? scale_bytes(nlos) : 0;
+    if (fused_peaks(p, precision))
+        b += (size_t)round_up(std::max<int64_t>(nlos, 1) * factored_peak_parts(*p) * (int64_t)sizeof(PeakPart), 256);
+    *bytes = b;
+    return rms_ok();
+}
+
+int rmsynth_execute_peaks(rmsynth_plan_t p, const float* Q, const float* U, int64_t nlos,
+                          int32_t layout, int32_t precision, float* Fq, float* Fu, float* Fabs,
+                          int32_t* idx, float* phi_pk, float* amp, float* q_pk, float* u_pk,
+                          void* workspace, size_t workspace_bytes, void* stream)
+{
+    const char* who = "rmsynth_execute_peaks";
+    if (int rc = check_execute_args(p, nlos, layout, precision, who)) return rc;
+    if (nlos == 0) return rms_ok();
+    if (!Q || !U || !Fq || !Fu || !idx) return rms_fail(RMSYNTH_EINVAL, "%s: NULL buffer", who);
+    size_t need = 0;
+    if (int rc = rmsynth_execute_peaks_workspace_size(p, nlos, layout, precision, &need)) return rc;
+    if (need && (!workspace || workspace_bytes < need))
+        return rms_fail(RMSYNTH_EWORKSPACE, "%s: needs %zu workspace bytes, got %zu", who, need,
+                        workspace ? workspace_bytes : (size_t)0);
+    if (int rc = check_device(p)) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    char* ws = static_cast<char*>(workspace);
+    float* scales = reinterpret_cast<float*>(ws);
+    const size_t sb = precision == RMSYNTH_SPLIT_FP16 ? scale_bytes(nlos) : 0;
+    if (!fused_peaks(p, precision)) {
+        if (int rc = run_execute(p, Q, U, nlos, layout, precision, Fq, Fu, Fabs, scales, nullptr, s, who))
+            return rc;
+        hipError_t e = launch_peaks(*p, Fq, Fu, nlos, idx, phi_pk, amp, q_pk, u_pk, s);
+        if (e != hipSuccess) return rms_hip_fail(e, who);
+        return rms_ok();
+    }
+    PeakPart* parts = reinterpret_cast<PeakPart*>(ws + sb);
+    if (int rc = run_execute(p, Q, U, nlos, layout, precision, Fq, Fu, Fabs, scales, parts, s, who))
+        return rc;
+    hipError_t e = launch_peak_merge(*p, parts, nlos, Fq, Fu, idx, phi_pk, amp, q_pk, u_pk, s);
+    if (e != hipSuccess) return rms_hip_fail(e, who);
     return rms_ok();
 }
 

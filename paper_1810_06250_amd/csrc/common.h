@@ -136,6 +136,12 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t bid, int64_t nblk)
 // ---------------------------------------------------------------------------
 // Kernel launchers (one per translation unit).  Each returns a hipError_t.
 // ---------------------------------------------------------------------------
+// Peak of |F|^2 of one LOS within 64 phi; idx = -2 marks a non-finite |F|^2.
+struct PeakPart {
+    float m;
+    int32_t idx;
+};
+
 struct ExecArgs {
     const float* Q;
     const float* U;
@@ -147,6 +153,7 @@ struct ExecArgs {
     float* Fu;
     float* Fabs;
     float* los_scale;  // FP16 split: per-LOS scale [nlos] in the workspace
+    PeakPart* peak_part;  // factored kernels: per-(LOS, phi tile) peaks, or NULL
     hipStream_t stream;
 };
 
@@ -159,6 +166,12 @@ hipError_t launch_peaks(const rmsynth_plan_s& p, const float* Fq, const float* F
                         int32_t* idx, float* phi_pk, float* amp, float* q_pk, float* u_pk,
                         hipStream_t s);
 hipError_t launch_rmsf(const rmsynth_plan_s& p, float* re, float* im, hipStream_t s);
+// Fused peaks of the factored kernels: records per LOS (one per half phi
+// tile), and the merge of the records into the rmsynth_peaks outputs.
+int factored_peak_parts(const rmsynth_plan_s& p);
+hipError_t launch_peak_merge(const rmsynth_plan_s& p, const PeakPart* part, int64_t nlos,
+                             const float* Fq, const float* Fu, int32_t* idx, float* phi_pk,
+                             float* amp, float* q_pk, float* u_pk, hipStream_t s);
 
 // Largest number of workgroups one launch may use (grid x dimension limit,
 // kept well inside 2^31 - 1).

@@ -13,10 +13,13 @@ hipError_t mlp_launch_head(const _Float16* H2, const float* Z2, int h2, const _F
                            const float* phi_label, const float* det_label, float* loss_b,
                            float* g_out, float* dz2, _Float16* dz2_16, float* phi_hat, float* score,
                            hipStream_t s);
+// Deterministic column reductions use a partial buffer of
+// mlp_reduce_part_floats(ncols) floats.
+int64_t mlp_reduce_part_floats(int64_t ncols);
 hipError_t mlp_launch_head_wgrad(const float* g, const _Float16* H2, int h2, int64_t nb, float alpha,
-                                 float* gW3, float* gb3, hipStream_t s);
+                                 float* gW3, float* gb3, float* part, hipStream_t s);
 hipError_t mlp_launch_colsum(const float* X, int64_t M, int64_t N, float alpha, float* out,
-                             hipStream_t s);
+                             float* part, hipStream_t s);
 hipError_t mlp_launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr,
                            float beta1, float beta2, float eps, float bc1, float bc2, hipStream_t s);
 hipError_t mlp_launch_weights16(const float* p, int64_t nW1, int64_t nb1, int64_t nW2, int64_t nb2,

@@ -199,35 +199,65 @@ __global__ __launch_bounds__(256) void head_kernel(
     }
 }
 
-// gW3[c][i] = alpha sum_b g[b][c] h2[b][i],  gb3[c] = alpha sum_b g[b][c];
-// one thread per output, sums in row order.
-__global__ void head_wgrad_kernel(const float* __restrict__ g, const _Float16* __restrict__ H2,
-                                  int h2, int64_t nb, float alpha, float* __restrict__ gW3,
-                                  float* __restrict__ gb3)
+// Deterministic column reductions in two levels: workgroup (x, y) sums the
+// rows of chunk y for 64 columns (four row phases, combined in a fixed
+// order) into part[y][n]; reduce_parts then adds the chunks in order.
+constexpr int RCH = 32;  // row chunks
+
+// part[y][n] = sum over rows m of chunk y of X[m][n].
+__global__ __launch_bounds__(256) void colsum_part_kernel(const float* __restrict__ X, int64_t M,
+                                                          int64_t N, float* __restrict__ part)
 {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx < 2 * h2) {
-        const int c = idx / h2, i = idx % h2;
-        float s = 0.0f;
-        for (int64_t b = 0; b < nb; ++b) s = __builtin_fmaf(g[2 * b + c], (float)H2[b * h2 + i], s);
-        gW3[idx] = alpha * s;
-    } else if (idx < 2 * h2 + 2) {
-        const int c = idx - 2 * h2;
-        float s = 0.0f;
-        for (int64_t b = 0; b < nb; ++b) s += g[2 * b + c];
-        gb3[c] = alpha * s;
-    }
+    __shared__ float red[4][64];
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int64_t n = (int64_t)blockIdx.x * 64 + tx;
+    const int64_t per = (M + RCH - 1) / RCH;
+    const int64_t m0 = blockIdx.y * per, m1 = m0 + per < M ? m0 + per : M;
+    float s = 0.0f;
+    if (n < N)
+        for (int64_t m = m0 + ty; m < m1; m += 4) s += X[m * N + n];
+    red[ty][tx] = s;
+    __syncthreads();
+    if (ty == 0 && n < N) part[blockIdx.y * N + n] = (red[0][tx] + red[1][tx]) + (red[2][tx] + red[3][tx]);
 }
 
-// out[n] = alpha sum_{m < M} X[m][n]  (column sums in row order).
-__global__ void colsum_kernel(const float* __restrict__ X, int64_t M, int64_t N, float alpha,
-                              float* __restrict__ out)
+// part[y][c h2 + i] = sum_b g[b][c] h2[b][i] and part[y][2 h2 + c] = sum_b g[b][c]
+// over the rows b of chunk y.
+__global__ __launch_bounds__(256) void head_wgrad_part_kernel(const float* __restrict__ g,
+                                                              const _Float16* __restrict__ H2,
+                                                              int h2, int64_t nb,
+                                                              float* __restrict__ part)
+{
+    __shared__ float red[4][64];
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int N = 2 * h2 + 2;
+    const int n = blockIdx.x * 64 + tx;
+    const int64_t per = (nb + RCH - 1) / RCH;
+    const int64_t b0 = blockIdx.y * per, b1 = b0 + per < nb ? b0 + per : nb;
+    float s = 0.0f;
+    if (n < 2 * h2) {
+        const int c = n / h2, i = n - c * h2;
+        for (int64_t b = b0 + ty; b < b1; b += 4) s = __builtin_fmaf(g[2 * b + c], (float)H2[b * h2 + i], s);
+    } else if (n < N) {
+        const int c = n - 2 * h2;
+        for (int64_t b = b0 + ty; b < b1; b += 4) s += g[2 * b + c];
+    }
+    red[ty][tx] = s;
+    __syncthreads();
+    if (ty == 0 && n < N) part[blockIdx.y * N + n] = (red[0][tx] + red[1][tx]) + (red[2][tx] + red[3][tx]);
+}
+
+// out[n] = alpha sum_y part[y][n] (chunks in order); with out2, columns
+// n >= split go to out2[n - split].
+__global__ void reduce_parts_kernel(const float* __restrict__ part, int64_t N, float alpha,
+                                    float* __restrict__ out, int64_t split, float* __restrict__ out2)
 {
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= N) return;
     float s = 0.0f;
-    for (int64_t m = 0; m < M; ++m) s += X[m * N + n];
-    out[n] = alpha * s;
+    for (int y = 0; y < RCH; ++y) s += part[y * N + n];
+    if (out2 && n >= split) out2[n - split] = alpha * s;
+    else out[n] = alpha * s;
 }
 
 // Adam (Kingma & Ba, bias-corrected) on the FP32 master parameters.
@@ -559,18 +589,27 @@ hipError_t mlp_launch_head(const _Float16* H2, const float* Z2, int h2, const _F
     return hipGetLastError();
 }
 
+int64_t mlp_reduce_part_floats(int64_t ncols) { return (int64_t)RCH * ncols; }
+
 hipError_t mlp_launch_head_wgrad(const float* g, const _Float16* H2, int h2, int64_t nb, float alpha,
-                                 float* gW3, float* gb3, hipStream_t s)
+                                 float* gW3, float* gb3, float* part, hipStream_t s)
 {
-    hipLaunchKernelGGL(head_wgrad_kernel, dim3(blocks_for(2 * h2 + 2, 64)), dim3(64), 0, s, g, H2, h2,
-                       nb, alpha, gW3, gb3);
+    const int N = 2 * h2 + 2;
+    hipLaunchKernelGGL(head_wgrad_part_kernel, dim3(blocks_for(N, 64), RCH), dim3(256), 0, s, g, H2, h2,
+                       nb, part);
+    if (hipError_t e = hipGetLastError()) return e;
+    hipLaunchKernelGGL(reduce_parts_kernel, dim3(blocks_for(N, 256)), dim3(256), 0, s, part,
+                       (int64_t)N, alpha, gW3, (int64_t)(2 * h2), gb3);
     return hipGetLastError();
 }
 
 hipError_t mlp_launch_colsum(const float* X, int64_t M, int64_t N, float alpha, float* out,
-                             hipStream_t s)
+                             float* part, hipStream_t s)
 {
-    hipLaunchKernelGGL(colsum_kernel, dim3(blocks_for(N, 64)), dim3(64), 0, s, X, M, N, alpha, out);
+    hipLaunchKernelGGL(colsum_part_kernel, dim3(blocks_for(N, 64), RCH), dim3(256), 0, s, X, M, N, part);
+    if (hipError_t e = hipGetLastError()) return e;
+    hipLaunchKernelGGL(reduce_parts_kernel, dim3(blocks_for(N, 256)), dim3(256), 0, s, part, N, alpha,
+                       out, N, nullptr);
     return hipGetLastError();
 }
 

@@ -29,6 +29,7 @@ struct rmsynth_mlp_s {
     float* d_m = nullptr;
     float* d_v = nullptr;
     _Float16* d_w16 = nullptr;   // W1 | W2 | W3 as half
+    float* d_part = nullptr;     // partial sums of the column reductions
     // Activation buffers, rows = capacity (multiple of 64).
     int64_t cap_fwd = 0, cap_bwd = 0;
     _Float16 *X = nullptr, *H1 = nullptr, *H2 = nullptr, *D2h = nullptr, *D1h = nullptr;
@@ -69,6 +70,7 @@ void free_mlp(rmsynth_mlp_s* m)
     free_acts(m);
     free_buf(m->d_chw); free_buf(m->d_p); free_buf(m->d_g); free_buf(m->d_m); free_buf(m->d_v);
     free_buf(m->d_w16);
+    free_buf(m->d_part);
     delete m;
 }
 
@@ -154,12 +156,12 @@ int gradient(rmsynth_mlp_s* m, const float* Q, const float* U, int64_t B, const 
                             phi, det, m->lossb, m->gout, m->D2, m->D2h, nullptr, nullptr, s);
     if (e == hipSuccess)
         e = mlp_launch_head_wgrad(m->gout, m->H2, m->h2, B, inv_b, m->d_g + m->off_W3(),
-                                  m->d_g + m->off_b3(), s);
+                                  m->d_g + m->off_b3(), m->d_part, s);
     // gW2[o][i] = sum_b dz2[b][o] h1[b][i]
     if (e == hipSuccess)
         e = mlp_launch_gemm(true, true, m->D2h, m->h2, m->H1, m->h1, m->h2, m->h1, rows, inv_b,
                             nullptr, false, nullptr, 0, m->d_g + m->off_W2(), m->h1, nullptr, 0, s);
-    if (e == hipSuccess) e = mlp_launch_colsum(m->D2, B, m->h2, inv_b, m->d_g + m->off_b2(), s);
+    if (e == hipSuccess) e = mlp_launch_colsum(m->D2, B, m->h2, inv_b, m->d_g + m->off_b2(), m->d_part, s);
     // dz1[b][i] = (sum_o dz2[b][o] W2[o][i]) * (z1[b][i] > 0)
     if (e == hipSuccess)
         e = mlp_launch_gemm(false, true, m->D2h, m->h2, W2h(m), m->h1, rows, m->h1, m->h2, 1.0f,
@@ -168,7 +170,7 @@ int gradient(rmsynth_mlp_s* m, const float* Q, const float* U, int64_t B, const 
     if (e == hipSuccess)
         e = mlp_launch_gemm(true, true, m->D1h, m->h1, m->X, m->nin_pad, m->h1, m->nin_pad, rows,
                             inv_b, nullptr, false, nullptr, 0, m->d_g, m->nin_pad, nullptr, 0, s);
-    if (e == hipSuccess) e = mlp_launch_colsum(m->D1, B, m->h1, inv_b, m->d_g + m->off_b1(), s);
+    if (e == hipSuccess) e = mlp_launch_colsum(m->D1, B, m->h1, inv_b, m->d_g + m->off_b1(), m->d_part, s);
     if (e == hipSuccess && loss) e = mlp_launch_mean(m->lossb, B, loss, s);
     if (e != hipSuccess) return rms_hip_fail(e, who);
     return RMSYNTH_OK;
@@ -272,7 +274,9 @@ int create(int32_t nchan, int32_t h1, int32_t h2, const float* weights, float ph
     if ((e = hipMalloc(&m->d_chw, sizeof(float) * nchan)) != hipSuccess ||
         (e = hipMalloc(&m->d_p, pb)) != hipSuccess || (e = hipMalloc(&m->d_g, pb)) != hipSuccess ||
         (e = hipMalloc(&m->d_m, pb)) != hipSuccess || (e = hipMalloc(&m->d_v, pb)) != hipSuccess ||
-        (e = hipMalloc(&m->d_w16, sizeof(_Float16) * (m->nW1 + m->nW2 + m->nW3))) != hipSuccess) {
+        (e = hipMalloc(&m->d_w16, sizeof(_Float16) * (m->nW1 + m->nW2 + m->nW3))) != hipSuccess ||
+        (e = hipMalloc(&m->d_part, sizeof(float) * mlp_reduce_part_floats(
+                                       std::max<int64_t>(std::max(h1, h2), 2 * (int64_t)h2 + 2)))) != hipSuccess) {
         free_mlp(m);
         return rms_fail(RMSYNTH_ENOMEM, "%s: hipMalloc: %s", who, hipGetErrorString(e));
     }

@@ -1,9 +1,11 @@
 // Per-LOS peak of |F| and the RM spread function.
 //
 // Peaks: one wave64 per LOS.  Each lane scans phi k = lane, lane + 64, ...
-// keeping the largest Fq^2 + Fu^2 (strict >, so its lowest k), then a
+// keeping the largest Fq^2 + Fu^2 (one rounding: fma(q, q, u * u), as the
+// fused peaks of the transform kernels; strict >, so its lowest k), then a
 // butterfly of cross-lane shuffles merges (value, index) pairs, ties going to
-// the lower index.  Any non-finite Fq or Fu marks the LOS (idx = -1).
+// the lower index.  A LOS whose |F|^2 is not finite somewhere (a non-finite
+// Fq or Fu, or |F|^2 beyond the FP32 range) is marked (idx = -1).
 // HBM-bound: 8 bytes read per (LOS, phi).
 //
 // RMSF, eq. (12): one thread per phi, FP64 argument reduction and FP32
@@ -36,15 +38,15 @@ __global__ __launch_bounds__(256) void peaks_kernel(
         for (int i = 0; i < 4; ++i) { a[i] = q[k + 64 * i]; b[i] = u[k + 64 * i]; }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            bad |= !(__builtin_fabsf(a[i]) <= FLT_MAX) || !(__builtin_fabsf(b[i]) <= FLT_MAX);
-            const float m = a[i] * a[i] + b[i] * b[i];
+            const float m = __builtin_fmaf(a[i], a[i], b[i] * b[i]);
+            bad |= !(m <= FLT_MAX);
             if (m > best) { best = m; bi = k + 64 * i; }
         }
     }
     for (; k < nphi; k += 64) {
         const float a = q[k], b = u[k];
-        bad |= !(__builtin_fabsf(a) <= FLT_MAX) || !(__builtin_fabsf(b) <= FLT_MAX);
-        const float m = a * a + b * b;
+        const float m = __builtin_fmaf(a, a, b * b);
+        bad |= !(m <= FLT_MAX);
         if (m > best) { best = m; bi = k; }
     }
 #pragma unroll

@@ -23,6 +23,8 @@
 // 64 columns = 4 x 2 blocks (128 accumulators per lane), so two workgroups
 // share a CU: while one waits on memory, a barrier or its output stores, the
 // other keeps the matrix cores busy.
+#include <float.h>
+
 #include "common.h"
 
 namespace {
@@ -66,13 +68,15 @@ __device__ __forceinline__ f32x16_t mfma16(uint4 a, uint4 b, f32x16_t c)
 // LOS-major input, rows are 16-byte aligned; the K-loop is then branch-free.
 // FLAGS: some channel has weight 0; its (zero) rotation then also clears
 // whatever the data hold there, NaN included.
-template <int LAYOUT, bool FP16, bool FAST, bool FLAGS>
+// PEAKS: the epilogue also reduces |F|^2 of every LOS over the tile's phi and
+// writes one PeakPart per (LOS, half of a phi tile) for peak_merge_kernel.
+template <int LAYOUT, bool FP16, bool FAST, bool FLAGS, bool PEAKS>
 __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
     const float* __restrict__ Q, const float* __restrict__ U, int64_t nlos, int64_t ld,
     int nchan, const float2* __restrict__ base, const uint4* __restrict__ Thi,
     const uint4* __restrict__ Tlo, int nchan_pad, int nk, int nphi, int tiles_n,
     float* __restrict__ Fq, float* __restrict__ Fu, float* __restrict__ Fabs,
-    const float* __restrict__ los_scale)
+    const float* __restrict__ los_scale, PeakPart* __restrict__ part)
 {
     // Triple-buffered A tiles (packed data) and T tiles (phase table).
     __shared__ ABuf abuf[3];
@@ -322,6 +326,88 @@ __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
                     }
             }
         }
+    if constexpr (PEAKS) {
+        // |F|^2 of the wave's 64 LOS x 64 phi (columns past the grid: -1) goes
+        // through the wave's own 8 KB of the data-tile buffers, which the main
+        // loop no longer uses (every wave has passed the last K-step's
+        // barrier), 32 columns at a time; lane j scans row j in phi order
+        // (strict >: ties to the lower phi) and writes one record per (LOS,
+        // 64-phi half tile).  A |F|^2 that is not finite marks the record.
+        float* sm = reinterpret_cast<float*>(&abuf[0]) + wave * (64 * 32);
+        float best = -1.0f;
+        int bk = 0;
+        bool bad = false;
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) {
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                for (int v = 0; v < 8; ++v) {
+                    const int row = 16 * rb + 8 * (v >> 2) + 4 * half + (v & 3);
+                    const float a = acc[rb][cb][v], b = acc[rb][cb][v + 8];
+                    const float m = __builtin_fmaf(a, a, b * b);
+                    sm[row * 32 + col] = nc + 32 * cb < nphi ? m : -1.0f;
+                }
+            __builtin_amdgcn_wave_barrier();
+            const float4* rowp = reinterpret_cast<const float4*>(sm + lane * 32);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const float4 m4 = rowp[q];
+                const float mm[4] = {m4.x, m4.y, m4.z, m4.w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    bad |= !(mm[e] <= FLT_MAX);
+                    if (mm[e] > best) {
+                        best = mm[e];
+                        bk = 32 * cb + 4 * q + e;
+                    }
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        const int64_t l = l0 + 64 * wr + lane;
+        if (l < nlos)
+            part[l * (2 * tiles_n) + 2 * tn + wc] = PeakPart{best, bad ? -2 : n0 + 64 * wc + bk};
+    }
+}
+
+// Merge the per-half-tile peaks of each LOS (in phi order, ties to the
+// earlier one, i.e. the lower phi index), then read Fq, Fu at the peak: the
+// same results as peaks_kernel on the stored outputs.
+__global__ void peak_merge_kernel(const PeakPart* __restrict__ part, int tiles_n, int64_t nlos,
+                                  int nphi, const double* __restrict__ phik,
+                                  const float* __restrict__ Fq, const float* __restrict__ Fu,
+                                  int32_t* __restrict__ idx, float* __restrict__ phi_pk,
+                                  float* __restrict__ amp, float* __restrict__ q_pk,
+                                  float* __restrict__ u_pk)
+{
+    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= nlos) return;
+    float best = -1.0f;
+    int bi = -1;
+    bool bad = false;
+    for (int t = 0; t < 2 * tiles_n; ++t) {
+        const PeakPart p = part[l * (2 * tiles_n) + t];
+        bad |= p.idx == -2;
+        if (p.m > best) {
+            best = p.m;
+            bi = p.idx;
+        }
+    }
+    if (bad || bi < 0 || bi >= nphi) {
+        idx[l] = -1;
+        const float nan = __builtin_nanf("");
+        if (phi_pk) phi_pk[l] = nan;
+        if (amp) amp[l] = nan;
+        if (q_pk) q_pk[l] = nan;
+        if (u_pk) u_pk[l] = nan;
+    } else {
+        idx[l] = bi;
+        if (phi_pk) phi_pk[l] = (float)phik[bi];
+        if (amp) amp[l] = sqrtf(best);
+        if (q_pk) q_pk[l] = Fq[l * nphi + bi];
+        if (u_pk) u_pk[l] = Fu[l * nphi + bi];
+    }
 }
 
 // Plan-time tables (FP64 argument reduction, FP32 sin/cos):
@@ -419,14 +505,19 @@ hipError_t launch_t(const rmsynth_plan_s& p, const ExecArgs& a)
     const uint4* Tlo = FP16 ? p.d_Thf[1] : p.d_Tbf[1];
     const bool full_k = p.nchan % KC == 0;
     const bool fast = full_k && (a.layout != RMSYNTH_LOS_MAJOR || a.vec4);
-#define RMS_LAUNCH(L, F, G)                                                                        \
-    hipLaunchKernelGGL((synth_factored_kernel<L, FP16, F, G>), dim3((unsigned)blocks), dim3(256), 0, \
-                       a.stream, a.Q, a.U, a.nlos, a.ld, p.nchan, p.d_base, Thi, Tlo,               \
-                       p.nchan_pad, nk, p.nphi, tiles_n, a.Fq, a.Fu, a.Fabs, a.los_scale)
-#define RMS_LAUNCH_G(L, F)                         \
+#define RMS_LAUNCH(L, F, G, P)                                                                        \
+    hipLaunchKernelGGL((synth_factored_kernel<L, FP16, F, G, P>), dim3((unsigned)blocks), dim3(256), 0, \
+                       a.stream, a.Q, a.U, a.nlos, a.ld, p.nchan, p.d_base, Thi, Tlo,                  \
+                       p.nchan_pad, nk, p.nphi, tiles_n, a.Fq, a.Fu, a.Fabs, a.los_scale, a.peak_part)
+#define RMS_LAUNCH_P(L, F, G)                      \
     do {                                           \
-        if (p.any_flagged) RMS_LAUNCH(L, F, true); \
-        else RMS_LAUNCH(L, F, false);              \
+        if (a.peak_part) RMS_LAUNCH(L, F, G, true); \
+        else RMS_LAUNCH(L, F, G, false);           \
+    } while (0)
+#define RMS_LAUNCH_G(L, F)                           \
+    do {                                             \
+        if (p.any_flagged) RMS_LAUNCH_P(L, F, true); \
+        else RMS_LAUNCH_P(L, F, false);              \
     } while (0)
     if (a.layout == RMSYNTH_LOS_MAJOR) {
         if (fast) RMS_LAUNCH_G(RMSYNTH_LOS_MAJOR, true);
@@ -436,6 +527,7 @@ hipError_t launch_t(const rmsynth_plan_s& p, const ExecArgs& a)
         else RMS_LAUNCH_G(RMSYNTH_FREQ_MAJOR, false);
     }
 #undef RMS_LAUNCH_G
+#undef RMS_LAUNCH_P
 #undef RMS_LAUNCH
     return hipGetLastError();
 }
@@ -468,5 +560,17 @@ hipError_t launch_factor_tables(const rmsynth_plan_s& p, hipStream_t stream)
     hipLaunchKernelGGL(factor_tables_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream,
                        p.d_b, p.d_w, p.nchan_pad, p.ftiles, p.phi0, p.dphi, p.K, p.d_base, p.d_Tbf[0],
                        p.d_Tbf[1], p.d_Thf[0], p.d_Thf[1]);
+    return hipGetLastError();
+}
+
+int factored_peak_parts(const rmsynth_plan_s& p) { return 2 * p.ftiles; }
+
+hipError_t launch_peak_merge(const rmsynth_plan_s& p, const PeakPart* part, int64_t nlos,
+                             const float* Fq, const float* Fu, int32_t* idx, float* phi_pk,
+                             float* amp, float* q_pk, float* u_pk, hipStream_t s)
+{
+    if (nlos <= 0) return hipSuccess;
+    hipLaunchKernelGGL(peak_merge_kernel, dim3((unsigned)((nlos + 255) / 256)), dim3(256), 0, s, part,
+                       p.ftiles, nlos, p.nphi, p.d_phi, Fq, Fu, idx, phi_pk, amp, q_pk, u_pk);
     return hipGetLastError();
 }

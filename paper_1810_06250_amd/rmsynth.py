@@ -45,6 +45,10 @@ SIGNATURES = {
     "rmsynth_rmsf": (ctypes.c_int, [_P, _P, _P, _P]),
     "rmsynth_execute": (ctypes.c_int, [_P, _P, _P, _I64, _I32, _I32, _P, _P, _P, _P, _SZ, _P]),
     "rmsynth_peaks": (ctypes.c_int, [_P, _P, _P, _I64, _P, _P, _P, _P, _P, _P]),
+    "rmsynth_execute_peaks": (ctypes.c_int, [_P, _P, _P, _I64, _I32, _I32, _P, _P, _P, _P, _P, _P,
+                                             _P, _P, _P, _SZ, _P]),
+    "rmsynth_execute_peaks_workspace_size": (ctypes.c_int, [_P, _I64, _I32, _I32,
+                                                            ctypes.POINTER(_SZ)]),
     "rmsynth_destroy": (None, [_P]),
     "rmsynth_last_error": (ctypes.c_char_p, []),
     "rmsynth_version": (ctypes.c_char_p, []),
@@ -178,6 +182,26 @@ def rmsynth_peaks(plan, Fq, Fu, nlos: int, idx, phi_pk=None, amp=None, q_pk=None
         plan, _dev(Fq, "Fq", f32), _dev(Fu, "Fu", f32), int(nlos), _dev(idx, "idx", torch.int32),
         _dev(phi_pk, "phi_pk", f32), _dev(amp, "amp", f32), _dev(q_pk, "q_pk", f32),
         _dev(u_pk, "u_pk", f32), _stream(stream)))
+
+
+def rmsynth_execute_peaks_workspace_size(plan, nlos: int, layout: int, precision: int) -> int:
+    b = ctypes.c_size_t()
+    _check("rmsynth_execute_peaks_workspace_size", load_library().rmsynth_execute_peaks_workspace_size(
+        plan, int(nlos), int(layout), int(precision), ctypes.byref(b)))
+    return b.value
+
+
+def rmsynth_execute_peaks(plan, Q, U, nlos: int, layout: int, precision: int, Fq, Fu, Fabs, idx,
+                          phi_pk=None, amp=None, q_pk=None, u_pk=None, workspace=None,
+                          workspace_bytes: int = 0, stream=None):
+    import torch
+    f32 = torch.float32
+    _check("rmsynth_execute_peaks", load_library().rmsynth_execute_peaks(
+        plan, _dev(Q, "Q", f32), _dev(U, "U", f32), int(nlos), int(layout), int(precision),
+        _dev(Fq, "Fq", f32), _dev(Fu, "Fu", f32), _dev(Fabs, "Fabs", f32),
+        _dev(idx, "idx", torch.int32), _dev(phi_pk, "phi_pk", f32), _dev(amp, "amp", f32),
+        _dev(q_pk, "q_pk", f32), _dev(u_pk, "u_pk", f32), _dev(workspace, "workspace"),
+        int(workspace_bytes), _stream(stream)))
 
 
 def rmsynth_destroy(plan):
@@ -356,6 +380,26 @@ class Plan:
         ws = torch.empty(ws_bytes, dtype=torch.uint8, device=Q.device) if ws_bytes else None
         rmsynth_execute(self.handle, Q, U, nlos, layout, precision, Fq, Fu, Fa, ws, ws_bytes)
         return Fq, Fu, Fa
+
+    def execute_peaks(self, Q, U, layout: int = RMSYNTH_LOS_MAJOR, precision: int = RMSYNTH_FP32,
+                      want_abs: bool = False):
+        """Transform and peaks in one call (rmsynth_execute_peaks)."""
+        import torch
+        nlos = Q.shape[0] if layout == RMSYNTH_LOS_MAJOR else Q.shape[1]
+        dev = Q.device
+        Fq = torch.empty((nlos, self.nphi), dtype=torch.float32, device=dev)
+        Fu = torch.empty_like(Fq)
+        Fa = torch.empty_like(Fq) if want_abs else None
+        out = dict(idx=torch.empty(nlos, dtype=torch.int32, device=dev),
+                   phi_pk=torch.empty(nlos, dtype=torch.float32, device=dev),
+                   amp=torch.empty(nlos, dtype=torch.float32, device=dev),
+                   q_pk=torch.empty(nlos, dtype=torch.float32, device=dev),
+                   u_pk=torch.empty(nlos, dtype=torch.float32, device=dev))
+        nb = rmsynth_execute_peaks_workspace_size(self.handle, nlos, layout, precision)
+        ws = torch.empty(nb, dtype=torch.uint8, device=dev) if nb else None
+        rmsynth_execute_peaks(self.handle, Q, U, nlos, layout, precision, Fq, Fu, Fa, out["idx"],
+                              out["phi_pk"], out["amp"], out["q_pk"], out["u_pk"], ws, nb)
+        return Fq, Fu, Fa, out
 
     def peaks(self, Fq, Fu):
         import torch

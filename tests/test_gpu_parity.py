@@ -251,6 +251,12 @@ def _full_size(name, prec_list, nsub):
         results[prec] = (err.max(), mism, bad)
         assert err.max() <= PREC_TOL[prec]
         assert mism == 0 and bad == 0
+        # The one-call transform + peaks gives the same peaks on the whole cube.
+        _, _, _, pk2 = plan.execute_peaks(cube["Q"], cube["U"], cube["layout"], PRECS[prec])
+        for key in ("idx", "amp", "q_pk", "u_pk"):
+            assert torch.equal(pk2[key], pk[key]), (name, prec, key)
+        del pk2
+        torch.cuda.empty_cache()
     del Fq, Fu, cube
     torch.cuda.empty_cache()
     return results
@@ -326,3 +332,63 @@ def test_fp16_split_wide_dynamic_range():
     out = _run(plan, dev32(Q), dev32(U), LOS_MAJOR, rs.RMSYNTH_SPLIT_FP16)
     _check(out, Q.astype(np.float64), U.astype(np.float64), c["lambda2"], c["weights"], c["phi"],
            LOS_MAJOR, PREC_TOL["fp16x3"])
+
+
+def _compare_fused(plan, Q, U, layout, prec):
+    import torch
+    Fq, Fu, _ = plan.execute(Q, U, layout, PRECS[prec])
+    pk = plan.peaks(Fq, Fu)
+    Fq2, Fu2, _, pk2 = plan.execute_peaks(Q, U, layout, PRECS[prec])
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(host(Fq2), host(Fq))
+    np.testing.assert_array_equal(host(Fu2), host(Fu))
+    for key in ("idx", "phi_pk", "amp", "q_pk", "u_pk"):
+        np.testing.assert_array_equal(host(pk2[key]), host(pk[key]), err_msg=f"{prec} {key}")
+    return host(pk2["idx"])
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp16x3", "fp32"])
+@pytest.mark.parametrize("layout", [LOS_MAJOR, FREQ_MAJOR], ids=["los", "freq"])
+@pytest.mark.parametrize("nlos,nchan,nphi", [(1000, 96, 300), (257, 33, 129), (128, 64, 2001)])
+def test_execute_peaks_equals_execute_then_peaks(prec, layout, nlos, nchan, nphi):
+    """rmsynth_execute_peaks (peaks reduced in the transform kernels' epilogue
+    and merged over phi tiles) gives bit for bit the outputs of rmsynth_execute
+    followed by rmsynth_peaks: ragged LOS and phi tiles, flagged channels, a
+    non-finite LOS."""
+    note(f"execute_peaks {prec} layout={layout} {nlos}x{nchan}x{nphi}")
+    c = make_small_cube(nlos, nchan, nphi, seed=nlos + nphi, nflag=5, nsrc=12)
+    Q, U = np.float32(c["Q"]), np.float32(c["U"])
+    unflagged = int(np.flatnonzero(c["weights"] > 0)[0])
+    flagged = int(np.flatnonzero(c["weights"] == 0)[0])
+    Q[3, unflagged] = np.nan        # poisons LOS 3
+    U[5, flagged] = np.inf          # ignored (weight 0)
+    plan = rs.Plan(c["lambda2"], c["weights"], np.linspace(-200, 200, nphi))
+    if layout == FREQ_MAJOR:
+        Q, U = np.ascontiguousarray(Q.T), np.ascontiguousarray(U.T)
+    idx = _compare_fused(plan, dev32(Q), dev32(U), layout, prec)
+    assert idx[3] == -1 and idx[5] >= 0
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp16x3"])
+def test_execute_peaks_all_ties_take_the_first_phi(prec):
+    """A zero cube: every |F| is 0, so every phi ties and the peak is phi_0."""
+    c = make_small_cube(300, 40, 700, seed=9)
+    plan = rs.Plan(c["lambda2"], c["weights"], np.linspace(-300, 300, 700))
+    Z = dev32(np.zeros((300, 40)))
+    idx = _compare_fused(plan, Z, Z, LOS_MAJOR, prec)
+    assert np.all(idx == 0)
+
+
+def test_execute_peaks_workspace_errors():
+    import torch
+    c = make_small_cube(8, 32, 300, seed=4)
+    plan = rs.Plan(c["lambda2"], c["weights"], np.linspace(-100, 100, 300))
+    need = rs.rmsynth_execute_peaks_workspace_size(plan.handle, 8, LOS_MAJOR, rs.RMSYNTH_SPLIT_BF16)
+    assert need >= 8 * 3 * 8   # one 8-byte record per LOS and phi tile
+    assert rs.rmsynth_execute_peaks_workspace_size(plan.handle, 8, LOS_MAJOR, rs.RMSYNTH_FP32) == 0
+    Q = dev32(c["Q"])
+    F = torch.empty((8, 300), dtype=torch.float32, device="cuda")
+    idx = torch.empty(8, dtype=torch.int32, device="cuda")
+    with pytest.raises(rs.RmsynthError) as ei:
+        rs.rmsynth_execute_peaks(plan.handle, Q, Q, 8, LOS_MAJOR, rs.RMSYNTH_SPLIT_BF16, F, F, None, idx)
+    assert ei.value.code == rs.rmsynth.RMSYNTH_EWORKSPACE
