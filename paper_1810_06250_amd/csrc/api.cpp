@@ -269,7 +269,8 @@ int run_execute(const rmsynth_plan_s* p, const float* Q, const float* U, int64_t
         a.Fu = Fu + l0 * p->nphi;
         a.Fabs = Fabs ? Fabs + l0 * p->nphi : nullptr;
         a.los_scale = precision == RMSYNTH_SPLIT_FP16 ? scales + l0 : nullptr;
-        a.peak_part = parts ? parts + l0 * factored_peak_parts(*p) : nullptr;
+        a.peak_part = parts ? parts + l0 : nullptr;
+        a.peak_part_ld = nlos;
         a.stream = stream;
         if (precision == RMSYNTH_SPLIT_FP16) {
             hipError_t e = launch_los_scale(*p, a);

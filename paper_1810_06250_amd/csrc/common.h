@@ -153,7 +153,8 @@ struct ExecArgs {
     float* Fu;
     float* Fabs;
     float* los_scale;  // FP16 split: per-LOS scale [nlos] in the workspace
-    PeakPart* peak_part;  // factored kernels: per-(LOS, phi tile) peaks, or NULL
+    PeakPart* peak_part;  // factored kernels: per-(LOS, half phi tile) peaks, or NULL;
+    int64_t peak_part_ld; // record (h, l) at peak_part[h * peak_part_ld + l]
     hipStream_t stream;
 };
 

@@ -69,14 +69,15 @@ __device__ __forceinline__ f32x16_t mfma16(uint4 a, uint4 b, f32x16_t c)
 // FLAGS: some channel has weight 0; its (zero) rotation then also clears
 // whatever the data hold there, NaN included.
 // PEAKS: the epilogue also reduces |F|^2 of every LOS over the tile's phi and
-// writes one PeakPart per (LOS, half of a phi tile) for peak_merge_kernel.
+// writes one PeakPart per (LOS, half of a phi tile) for peak_merge_kernel,
+// at part[half tile * part_ld + LOS].
 template <int LAYOUT, bool FP16, bool FAST, bool FLAGS, bool PEAKS>
 __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
     const float* __restrict__ Q, const float* __restrict__ U, int64_t nlos, int64_t ld,
     int nchan, const float2* __restrict__ base, const uint4* __restrict__ Thi,
     const uint4* __restrict__ Tlo, int nchan_pad, int nk, int nphi, int tiles_n,
     float* __restrict__ Fq, float* __restrict__ Fu, float* __restrict__ Fabs,
-    const float* __restrict__ los_scale, PeakPart* __restrict__ part)
+    const float* __restrict__ los_scale, PeakPart* __restrict__ part, int64_t part_ld)
 {
     // Triple-buffered A tiles (packed data) and T tiles (phase table).
     __shared__ ABuf abuf[3];
@@ -333,7 +334,8 @@ __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
         // barrier), 32 columns at a time; lane j scans row j in phi order
         // (strict >: ties to the lower phi) and writes one record per (LOS,
         // 64-phi half tile).  A |F|^2 that is not finite marks the record.
-        float* sm = reinterpret_cast<float*>(&abuf[0]) + wave * (64 * 32);
+        constexpr int SR = 36;  // row stride (floats): conflict-free b128 row reads
+        float* sm = reinterpret_cast<float*>(&abuf[0]) + wave * (64 * SR);
         float best = -1.0f;
         int bk = 0;
         bool bad = false;
@@ -346,10 +348,10 @@ __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
                     const int row = 16 * rb + 8 * (v >> 2) + 4 * half + (v & 3);
                     const float a = acc[rb][cb][v], b = acc[rb][cb][v + 8];
                     const float m = __builtin_fmaf(a, a, b * b);
-                    sm[row * 32 + col] = nc + 32 * cb < nphi ? m : -1.0f;
+                    sm[row * SR + col] = nc + 32 * cb < nphi ? m : -1.0f;
                 }
             __builtin_amdgcn_wave_barrier();
-            const float4* rowp = reinterpret_cast<const float4*>(sm + lane * 32);
+            const float4* rowp = reinterpret_cast<const float4*>(sm + lane * SR);
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 const float4 m4 = rowp[q];
@@ -366,15 +368,14 @@ __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
             __builtin_amdgcn_wave_barrier();
         }
         const int64_t l = l0 + 64 * wr + lane;
-        if (l < nlos)
-            part[l * (2 * tiles_n) + 2 * tn + wc] = PeakPart{best, bad ? -2 : n0 + 64 * wc + bk};
+        if (l < nlos) part[(2 * tn + wc) * part_ld + l] = PeakPart{best, bad ? -2 : n0 + 64 * wc + bk};
     }
 }
 
 // Merge the per-half-tile peaks of each LOS (in phi order, ties to the
 // earlier one, i.e. the lower phi index), then read Fq, Fu at the peak: the
 // same results as peaks_kernel on the stored outputs.
-__global__ void peak_merge_kernel(const PeakPart* __restrict__ part, int tiles_n, int64_t nlos,
+__global__ void peak_merge_kernel(const PeakPart* __restrict__ part, int nparts, int64_t nlos,
                                   int nphi, const double* __restrict__ phik,
                                   const float* __restrict__ Fq, const float* __restrict__ Fu,
                                   int32_t* __restrict__ idx, float* __restrict__ phi_pk,
@@ -386,8 +387,8 @@ __global__ void peak_merge_kernel(const PeakPart* __restrict__ part, int tiles_n
     float best = -1.0f;
     int bi = -1;
     bool bad = false;
-    for (int t = 0; t < 2 * tiles_n; ++t) {
-        const PeakPart p = part[l * (2 * tiles_n) + t];
+    for (int t = 0; t < nparts; ++t) {
+        const PeakPart p = part[t * nlos + l];
         bad |= p.idx == -2;
         if (p.m > best) {
             best = p.m;
@@ -508,7 +509,8 @@ hipError_t launch_t(const rmsynth_plan_s& p, const ExecArgs& a)
 #define RMS_LAUNCH(L, F, G, P)                                                                        \
     hipLaunchKernelGGL((synth_factored_kernel<L, FP16, F, G, P>), dim3((unsigned)blocks), dim3(256), 0, \
                        a.stream, a.Q, a.U, a.nlos, a.ld, p.nchan, p.d_base, Thi, Tlo,                  \
-                       p.nchan_pad, nk, p.nphi, tiles_n, a.Fq, a.Fu, a.Fabs, a.los_scale, a.peak_part)
+                       p.nchan_pad, nk, p.nphi, tiles_n, a.Fq, a.Fu, a.Fabs, a.los_scale, a.peak_part,  \
+                       a.peak_part_ld)
 #define RMS_LAUNCH_P(L, F, G)                      \
     do {                                           \
         if (a.peak_part) RMS_LAUNCH(L, F, G, true); \
@@ -571,6 +573,6 @@ hipError_t launch_peak_merge(const rmsynth_plan_s& p, const PeakPart* part, int6
 {
     if (nlos <= 0) return hipSuccess;
     hipLaunchKernelGGL(peak_merge_kernel, dim3((unsigned)((nlos + 255) / 256)), dim3(256), 0, s, part,
-                       p.ftiles, nlos, p.nphi, p.d_phi, Fq, Fu, idx, phi_pk, amp, q_pk, u_pk);
+                       2 * p.ftiles, nlos, p.nphi, p.d_phi, Fq, Fu, idx, phi_pk, amp, q_pk, u_pk);
     return hipGetLastError();
 }
