@@ -38,7 +38,7 @@ METRIC = "LOS·chan·φ Gsamples/s + % MFMA peak, split-BF16 vs FP32 at ≤1e-5 
 # taken on).  A changed kernel source reports null until counters are retaken.
 KERNEL_SRC = os.path.join(ROOT, "paper_1810_06250_amd", "csrc", "synth_factored.hip")
 TRAFFIC = {
-    ("c3", "bf16x3", "273236c18bfb36f0"): 2.0 * 2324961 * 1024 + 1.0 * 17081900 * 1024,
+    ("c3", "bf16x3", "62ab363165bf9a7c"): 2.0 * 2400199 * 1024 + 1.0 * 17000780 * 1024,
 }
 
 
@@ -64,6 +64,8 @@ def parse():
     ap.add_argument("--no-gate", action="store_true",
                     help="skip the learned-gate leg (c5 band: train, calibrate, gated search)")
     ap.add_argument("--gate-train", type=int, default=1_000_000)
+    ap.add_argument("--no-gemm-ref", action="store_true",
+                    help="skip timing the vendor bf16 GEMM used as a practical MFMA reference")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB "
                          "(a known-size reference for HBM byte counters)")
@@ -72,6 +74,28 @@ def parse():
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def gemm_reference(n=16384, reps=5):
+    """Throughput of a plain bf16 GEMM from the vendor library (torch.matmul,
+    n x n x n): what the matrix cores sustain on this board for the plainest
+    dense contraction, as context for the split kernel's MFMA rate."""
+    import torch
+    a = torch.randn(n, n, device="cuda", dtype=torch.bfloat16)
+    b = torch.randn(n, n, device="cuda", dtype=torch.bfloat16)
+    for _ in range(2):
+        c = a @ b
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        c = a @ b
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b, c
+    torch.cuda.empty_cache()
+    return 2.0 * n ** 3 / (ms * 1e-3) / 1e12, ms
 
 
 def time_path(rs, plan, cube, prec, Fq, Fu, pk, steps, warmup, fused=False):
@@ -400,6 +424,13 @@ def main():
             del Fq2, Fu2, pk2
         torch.cuda.empty_cache()
         res["learned_gate"] = gate_leg(rs, args.gate_train)
+    if not args.no_gemm_ref and args.precision == "bf16x3":
+        log("reference: vendor bf16 GEMM 16384^3")
+        tf, ms = gemm_reference()
+        res["mfma_reference"] = {
+            "kind": "torch.matmul bf16, 16384 x 16384 x 16384 (vendor GEMM library), same run",
+            "ms": ms, "tflops": tf, "frac_of_peak": tf / MFMA_PEAK_TFLOPS["bf16x3"],
+            "split_kernel_vs_reference": achieved / tf}
     print(json.dumps(res), flush=True)
     plan.close()
     return 0

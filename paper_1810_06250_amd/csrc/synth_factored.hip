@@ -13,16 +13,19 @@
 //
 // Contraction: v_mfma_f32_32x32x16_{bf16,f16}, hi*hi + hi*lo + lo*hi with FP32
 // accumulation.  Real form of eqs. (15)-(16): A rows (x', y') and (y', -x')
-// per LOS, B columns (cos, sin) of T.  In A, each 32-row MFMA block holds the
-// real-part rows of 16 LOS followed by their imaginary-part rows, so Re F and
-// Im F of a LOS land in the same lane (accumulators v and v + 8).
+// per LOS, B columns (cos, sin) of T.  LDS holds only the (x', y') rows; the
+// (y', -x') fragment is derived in registers (halves swapped, one sign
+// flipped: one packed 16-bit add per register), which halves the A traffic
+// through LDS.  Re F and Im F of a LOS land in the same lane and register of
+// two accumulators.
 //
 // Workgroup: 256 threads, 128 LOS x 128 phi, 8 channels per K-step (one MFMA
-// K of 16), LDS triple buffered (3 x 24 KB) so that the first fragments of a
-// K-step are read before the barrier that ends the previous one.  Waves 2 x 2, each 128 rows x
-// 64 columns = 4 x 2 blocks (128 accumulators per lane), so two workgroups
-// share a CU: while one waits on memory, a barrier or its output stores, the
-// other keeps the matrix cores busy.
+// K of 16), LDS triple buffered (3 x 16 KB) so that the first fragments of a
+// K-step are read before the barrier that ends the previous one.  Waves 2 x 2,
+// each 64 LOS x 64 phi = 2 LOS groups x (Re, Im) x 2 phi blocks (128
+// accumulators per lane), so two workgroups share a CU: while one waits on
+// memory, a barrier or its output stores, the other keeps the matrix cores
+// busy.  Q/U loads run two K-steps ahead of their use.
 #include <float.h>
 
 #include "common.h"
@@ -30,14 +33,13 @@
 namespace {
 
 constexpr int MT = 128;          // LOS per tile
-constexpr int ROWS = 2 * MT;     // A rows
 constexpr int NT = kFactorTile;  // phi per tile
 constexpr int KC = 8;            // channels per K-step
 constexpr int NQ = KC / 4;       // channel quads per K-step
 
 struct ABuf {
-    uint4 a_hi[NQ][ROWS];
-    uint4 a_lo[NQ][ROWS];
+    uint4 a_hi[NQ][MT];
+    uint4 a_lo[NQ][MT];
 };
 struct BBuf {
     uint4 b_hi[NQ][NT];
@@ -51,6 +53,24 @@ __device__ __forceinline__ void split2(float a, float b, uint32_t& hi, uint32_t&
 {
     if (FP16) split2_f16(a, b, hi, lo);
     else split2_bf16(a, b, hi, lo);
+}
+
+typedef unsigned short u16x2_t __attribute__((ext_vector_type(2)));
+
+// (x, y) -> (y, -x) on a pair of 16-bit floats: the halves swapped and the new
+// high half's sign flipped, as one packed 16-bit add of (0, 0x8000) to the
+// swapped pair.  neg_hi must be 0x80000000; it arrives as a kernel argument so
+// that the add is not rewritten into a swap followed by an XOR.
+__device__ __forceinline__ uint32_t swap_neg(uint32_t d, uint32_t neg_hi)
+{
+    const u16x2_t v = __builtin_bit_cast(u16x2_t, d);
+    const u16x2_t sw = __builtin_shufflevector(v, v, 1, 0);
+    return __builtin_bit_cast(uint32_t, sw + __builtin_bit_cast(u16x2_t, neg_hi));
+}
+__device__ __forceinline__ uint4 swap_neg4(uint4 d, uint32_t neg_hi)
+{
+    return make_uint4(swap_neg(d.x, neg_hi), swap_neg(d.y, neg_hi), swap_neg(d.z, neg_hi),
+                      swap_neg(d.w, neg_hi));
 }
 
 template <bool FP16>
@@ -77,11 +97,18 @@ __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
     int nchan, const float2* __restrict__ base, const uint4* __restrict__ Thi,
     const uint4* __restrict__ Tlo, int nchan_pad, int nk, int nphi, int tiles_n,
     float* __restrict__ Fq, float* __restrict__ Fu, float* __restrict__ Fabs,
-    const float* __restrict__ los_scale, PeakPart* __restrict__ part, int64_t part_ld)
+    const float* __restrict__ los_scale, PeakPart* __restrict__ part, int64_t part_ld,
+    uint32_t neg_hi)
 {
-    // Triple-buffered A tiles (packed data) and T tiles (phase table).
-    __shared__ ABuf abuf[3];
-    __shared__ BBuf bbuf[3];
+    // Triple-buffered A tiles (packed data) and T tiles (phase table), in one
+    // block so that the epilogue can reuse all of it.
+    struct Lds {
+        ABuf a[3];
+        BBuf b[3];
+    };
+    __shared__ Lds lds;
+    ABuf* const abuf = lds.a;
+    BBuf* const bbuf = lds.b;
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const int64_t tm = tile / tiles_n;
     const int tn = (int)(tile - tm * tiles_n);
@@ -98,20 +125,19 @@ __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
     const int64_t lg = l0 + la;
     // Rows past the cube read the last LOS (in bounds); their outputs are never stored.
     const int64_t lr = lg < nlos ? lg : nlos - 1;
-    const int rre = 32 * (la >> 4) + (la & 15);  // real-part row; imaginary row is +16
     // FP16: per-LOS power-of-two scale that keeps both halves of the split in
     // half precision's normal range; undone exactly in the epilogue.
     const float lsc = FP16 ? los_scale[lr] : 1.0f;
     const_f4_ptr bt = (const_f4_ptr)(base + (int64_t)tn * nchan_pad);
 
     // Q/U and channel rotations of one K-step (4 channels of this thread),
-    // held in registers; two sets alternate so loads run two K-steps ahead.
+    // held in registers; three sets rotate (see the K-loop below).
     struct Regs {
         float q[4], u[4];
         f32x4_t rot[2];  // K w_j (cos, sin) of theta_{j,k0}, 2 channels per vector
         uint4 th, tl;    // this thread's 16-byte share of the K-step's T tile
     };
-    Regs R0, R1;
+    Regs R0, R1, R2;
 
     auto gload = [&](Regs& R, int ks) {
         const int j0 = ks * KC + 4 * hh;
@@ -168,21 +194,20 @@ __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
         (&b.b_lo[0][0])[t] = R.tl;
     };
     auto store_a = [&](ABuf& b) {
-        b.a_hi[hh][rre] = make_uint4(hi[0], hi[1], hi[2], hi[3]);
-        b.a_lo[hh][rre] = make_uint4(lo[0], lo[1], lo[2], lo[3]);
-        b.a_hi[hh][rre + 16] = make_uint4(swap_negate(hi[0]), swap_negate(hi[1]),
-                                          swap_negate(hi[2]), swap_negate(hi[3]));
-        b.a_lo[hh][rre + 16] = make_uint4(swap_negate(lo[0]), swap_negate(lo[1]),
-                                          swap_negate(lo[2]), swap_negate(lo[3]));
+        b.a_hi[hh][la] = make_uint4(hi[0], hi[1], hi[2], hi[3]);
+        b.a_lo[hh][la] = make_uint4(lo[0], lo[1], lo[2], lo[3]);
     };
 
-    f32x16_t acc[4][2];
+    // acc[g][p][cb]: LOS group g (32 LOS), part p (0: Re F, 1: Im F), phi block cb.
+    f32x16_t acc[2][2][2];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int g = 0; g < 2; ++g)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int p = 0; p < 2; ++p)
 #pragma unroll
-            for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int v = 0; v < 16; ++v) acc[g][p][j][v] = 0.0f;
 
     const int r = lane & 31, hsel = lane >> 5;
     // First fragments of a K-step (both B column blocks, A row block 0),
@@ -196,29 +221,43 @@ __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
             F.bh[cb] = b.b_hi[hsel][64 * wc + 32 * cb + r];
             F.bl[cb] = b.b_lo[hsel][64 * wc + 32 * cb + r];
         }
-        F.ah = a.a_hi[hsel][128 * wr + r];
-        F.al = a.a_lo[hsel][128 * wr + r];
+        F.ah = a.a_hi[hsel][64 * wr + r];
+        F.al = a.a_lo[hsel][64 * wr + r];
     };
     // One K-step of MFMAs (8 channels = one K of 16) from buffer `cur` with
     // first fragments F, the packing of a later K-step (registers P)
     // interleaved one channel after each row block; the next row block's A
     // fragments are read ahead.
+    // The real-part rows (x', y') of a LOS group come from LDS; the
+    // imaginary-part rows (y', -x') are derived from them in registers.
     auto mma = [&](const ABuf& cur, const Frag& F, const Regs& P) {
-        uint4 ahn = F.ah, aln = F.al;
+        uint4 ah = F.ah, al = F.al;
 #pragma unroll
-        for (int rb = 0; rb < 4; ++rb) {
-            const uint4 ah = ahn, al = aln;
-            if (rb < 3) {
-                ahn = cur.a_hi[hsel][128 * wr + 32 * (rb + 1) + r];
-                aln = cur.a_lo[hsel][128 * wr + 32 * (rb + 1) + r];
+        for (int g = 0; g < 2; ++g) {
+            uint4 ahn, aln;
+            if (g == 0) {
+                ahn = cur.a_hi[hsel][64 * wr + 32 + r];
+                aln = cur.a_lo[hsel][64 * wr + 32 + r];
             }
+            const uint4 ih = swap_neg4(ah, neg_hi), il = swap_neg4(al, neg_hi);
 #pragma unroll
             for (int cb = 0; cb < 2; ++cb) {
-                acc[rb][cb] = mfma16<FP16>(al, F.bh[cb], acc[rb][cb]);
-                acc[rb][cb] = mfma16<FP16>(ah, F.bl[cb], acc[rb][cb]);
-                acc[rb][cb] = mfma16<FP16>(ah, F.bh[cb], acc[rb][cb]);
+                acc[g][0][cb] = mfma16<FP16>(al, F.bh[cb], acc[g][0][cb]);
+                acc[g][0][cb] = mfma16<FP16>(ah, F.bl[cb], acc[g][0][cb]);
+                acc[g][0][cb] = mfma16<FP16>(ah, F.bh[cb], acc[g][0][cb]);
             }
-            pack1(P, rb);
+            pack1(P, 2 * g);
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb) {
+                acc[g][1][cb] = mfma16<FP16>(il, F.bh[cb], acc[g][1][cb]);
+                acc[g][1][cb] = mfma16<FP16>(ih, F.bl[cb], acc[g][1][cb]);
+                acc[g][1][cb] = mfma16<FP16>(ih, F.bh[cb], acc[g][1][cb]);
+            }
+            pack1(P, 2 * g + 1);
+            if (g == 0) {
+                ah = ahn;
+                al = aln;
+            }
         }
     };
 
@@ -232,15 +271,16 @@ __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
     // while K-step k + 2 is packed into buffer (k + 2) % 3 (last read in step
     // k - 1, before the previous barrier) and the first fragments of k + 1
     // are read from buffer (k + 1) % 3 (complete since the previous barrier).
-    // Two register sets alternate: step k packs R[k % 2] (K-step k + 2) and
-    // loads K-step k + 3 into R[(k + 1) % 2].  Load indices past the end are
-    // clamped to the last K-step (loaded, never stored).
+    // Three register sets rotate so that loads run two K-steps ahead of their
+    // use: step k packs K-step k + 2 and loads K-step k + 4 into the set the
+    // previous step packed.  Load indices past the end are clamped to the
+    // last K-step (loaded, never stored).
     Frag F;
     int bc = 0;  // buffer of K-step k; (bc + 1) % 3 and (bc + 2) % 3 follow
     auto step = [&](Regs& Rp, Regs& Rl, int k) {
         const int bf = bc == 2 ? 0 : bc + 1;
         const int bn = bf == 2 ? 0 : bf + 1;
-        gload(Rl, k + 3 < nk ? k + 3 : nk - 1);
+        gload(Rl, k + 4 < nk ? k + 4 : nk - 1);
         __builtin_amdgcn_sched_barrier(0);
         mma(abuf[bc], F, Rp);
         // Unconditional: past the last K-step these write a buffer nobody
@@ -258,8 +298,9 @@ __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
         bc = bf;
     };
 
-    // Prologue: K-steps 0 and 1 packed into buffers 0 and 1, K-step 2 loading
-    // into R0, the first fragments of K-step 0 read after the barrier.
+    // Prologue: K-steps 0 and 1 packed into buffers 0 and 1, K-steps 2 and 3
+    // loading into R0 and R2, the first fragments of K-step 0 read after the
+    // barrier.
     gload(R0, 0);
     gload(R1, nk > 1 ? 1 : 0);
 #pragma unroll
@@ -271,33 +312,36 @@ __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
     store_a(abuf[1]);
     store_t(bbuf[1], R1);
     gload(R0, nk > 2 ? 2 : nk - 1);
+    gload(R2, nk > 3 ? 3 : nk - 1);
     sync_next();
     load_frag(F, abuf[0], bbuf[0]);
 
     int k = 0;
-    for (; k + 1 < nk; k += 2) {
+    for (; k + 2 < nk; k += 3) {
         step(R0, R1, k);
-        step(R1, R0, k + 1);
+        step(R2, R0, k + 1);
+        step(R1, R2, k + 2);
     }
     if (k < nk) step(R0, R1, k);
+    if (k + 1 < nk) step(R2, R0, k + 1);
 
-    // Epilogue: block rb holds LOS 64 wr + 16 rb + i; Re F in v < 8, Im F in v + 8.
+    // Epilogue: group g holds LOS 64 wr + 32 g + i, Re F in acc[g][0], Im F in acc[g][1].
     // Tiles wholly inside the output (the common case) store without checks.
     const int half = lane >> 5, col = lane & 31;
     const int nc = n0 + 64 * wc + col;
     const bool full = (l0 + MT <= nlos) && (n0 + NT <= nphi);
 #pragma unroll
-    for (int rb = 0; rb < 4; ++rb)
+    for (int g = 0; g < 2; ++g)
 #pragma unroll
-        for (int v = 0; v < 8; ++v) {
+        for (int v = 0; v < 16; ++v) {
             const int i = 8 * (v >> 2) + 4 * half + (v & 3);
-            const int64_t l = l0 + 64 * wr + 16 * rb + i;
+            const int64_t l = l0 + 64 * wr + 32 * g + i;
             if (FP16) {
                 const float inv = 1.0f / los_scale[l < nlos ? l : nlos - 1];
 #pragma unroll
                 for (int cb = 0; cb < 2; ++cb) {
-                    acc[rb][cb][v] *= inv;
-                    acc[rb][cb][v + 8] *= inv;
+                    acc[g][0][cb][v] *= inv;
+                    acc[g][1][cb][v] *= inv;
                 }
             }
             const int64_t off = l * nphi + nc;
@@ -306,15 +350,15 @@ __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
             if (full) {
 #pragma unroll
                 for (int cb = 0; cb < 2; ++cb) {
-                    fq[32 * cb] = acc[rb][cb][v];
-                    fu[32 * cb] = acc[rb][cb][v + 8];
+                    fq[32 * cb] = acc[g][0][cb][v];
+                    fu[32 * cb] = acc[g][1][cb][v];
                 }
             } else if (l < nlos) {
 #pragma unroll
                 for (int cb = 0; cb < 2; ++cb)
                     if (nc + 32 * cb < nphi) {
-                        fq[32 * cb] = acc[rb][cb][v];
-                        fu[32 * cb] = acc[rb][cb][v + 8];
+                        fq[32 * cb] = acc[g][0][cb][v];
+                        fu[32 * cb] = acc[g][1][cb][v];
                     }
             }
             if (Fabs && l < nlos) {
@@ -322,31 +366,31 @@ __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
 #pragma unroll
                 for (int cb = 0; cb < 2; ++cb)
                     if (nc + 32 * cb < nphi) {
-                        const float a = acc[rb][cb][v], b = acc[rb][cb][v + 8];
+                        const float a = acc[g][0][cb][v], b = acc[g][1][cb][v];
                         fa[32 * cb] = sqrtf(a * a + b * b);
                     }
             }
         }
     if constexpr (PEAKS) {
         // |F|^2 of the wave's 64 LOS x 64 phi (columns past the grid: -1) goes
-        // through the wave's own 8 KB of the data-tile buffers, which the main
+        // through the wave's own 9 KB of the LDS block, which the main
         // loop no longer uses (every wave has passed the last K-step's
         // barrier), 32 columns at a time; lane j scans row j in phi order
         // (strict >: ties to the lower phi) and writes one record per (LOS,
         // 64-phi half tile).  A |F|^2 that is not finite marks the record.
         constexpr int SR = 36;  // row stride (floats): conflict-free b128 row reads
-        float* sm = reinterpret_cast<float*>(&abuf[0]) + wave * (64 * SR);
+        float* sm = reinterpret_cast<float*>(&lds) + wave * (64 * SR);
         float best = -1.0f;
         int bk = 0;
         bool bad = false;
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb) {
 #pragma unroll
-            for (int rb = 0; rb < 4; ++rb)
+            for (int g = 0; g < 2; ++g)
 #pragma unroll
-                for (int v = 0; v < 8; ++v) {
-                    const int row = 16 * rb + 8 * (v >> 2) + 4 * half + (v & 3);
-                    const float a = acc[rb][cb][v], b = acc[rb][cb][v + 8];
+                for (int v = 0; v < 16; ++v) {
+                    const int row = 32 * g + 8 * (v >> 2) + 4 * half + (v & 3);
+                    const float a = acc[g][0][cb][v], b = acc[g][1][cb][v];
                     const float m = __builtin_fmaf(a, a, b * b);
                     sm[row * SR + col] = nc + 32 * cb < nphi ? m : -1.0f;
                 }
@@ -510,7 +554,7 @@ hipError_t launch_t(const rmsynth_plan_s& p, const ExecArgs& a)
     hipLaunchKernelGGL((synth_factored_kernel<L, FP16, F, G, P>), dim3((unsigned)blocks), dim3(256), 0, \
                        a.stream, a.Q, a.U, a.nlos, a.ld, p.nchan, p.d_base, Thi, Tlo,                  \
                        p.nchan_pad, nk, p.nphi, tiles_n, a.Fq, a.Fu, a.Fabs, a.los_scale, a.peak_part,  \
-                       a.peak_part_ld)
+                       a.peak_part_ld, 0x80000000u)
 #define RMS_LAUNCH_P(L, F, G)                      \
     do {                                           \
         if (a.peak_part) RMS_LAUNCH(L, F, G, true); \
