@@ -91,7 +91,11 @@ int rmsynth_mlp_train_step(rmsynth_mlp_t mlp, const float* Q, const float* U, in
 /*
  * rmsynth_mlp_infer -- phi_hat and detection score for nlos >= 0 lines of
  * sight (device [nlos] each).  A non-finite unflagged input gives NaN
- * outputs.  Works in chunks through the object's buffers.
+ * outputs.  Hidden widths 256 and 256 run as one fused kernel per call (the
+ * first call after a parameter change also rebuilds, on `stream`, the
+ * object's copy of W1 and W2 in matrix-core fragment order); other widths
+ * work in chunks through the object's buffers.  An object is not to be used
+ * from several host threads at once.
  */
 int rmsynth_mlp_infer(rmsynth_mlp_t mlp, const float* Q, const float* U, int64_t nlos,
                       float* phi_hat, float* score, void* stream);

@@ -15,6 +15,17 @@
 
 namespace {
 
+// FP32 to half, the FP32 value rounded first: the empty asm keeps the
+// compiler from fusing the multiply or add that produced x and the
+// conversion into one mixed-precision FMA (a single rounding from the exact
+// result), so every half below is the nearest half to an FP32 number, in the
+// training kernels and in fused inference alike.
+__device__ __forceinline__ _Float16 half_of(float x)
+{
+    asm volatile("" : "+v"(x));
+    return (_Float16)x;
+}
+
 // ----------------------------------------------------------------- input
 // One wave per row.  Rows b < nvalid: x = [w Q | w U] / rms (half), columns
 // [2 nchan, ldx) zero.  Rows nvalid <= b < nrows: all zero (batch padding).
@@ -46,8 +57,8 @@ __global__ __launch_bounds__(256) void input_kernel(const float* __restrict__ Q,
     const float inv = ss > 0.0f ? 1.0f / sqrtf(ss / (float)(2 * nchan))
                                 : (ss == 0.0f ? 0.0f : ss);  // NaN stays NaN
     for (int j = lane; j < nchan; j += 64) {
-        x[j] = (_Float16)(w[j] == 0.0f ? 0.0f : w[j] * q[j] * inv);
-        x[nchan + j] = (_Float16)(w[j] == 0.0f ? 0.0f : w[j] * u[j] * inv);
+        x[j] = half_of(w[j] == 0.0f ? 0.0f : w[j] * q[j] * inv);
+        x[nchan + j] = half_of(w[j] == 0.0f ? 0.0f : w[j] * u[j] * inv);
     }
     for (int j = 2 * nchan + lane; j < ldx; j += 64) x[j] = (_Float16)0.0f;
 }
@@ -131,7 +142,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(
         float z = __builtin_fmaf(alpha, acc[v], bn);
         if (mask && !(mask[m * ldm + n] > 0.0f)) z = 0.0f;
         if (C32) C32[m * ldc + n] = z;
-        if (C16) C16[m * ldc16 + n] = (_Float16)((relu && z < 0.0f) ? 0.0f : z);
+        if (C16) C16[m * ldc16 + n] = half_of((relu && z < 0.0f) ? 0.0f : z);
     }
 }
 
@@ -195,7 +206,7 @@ __global__ __launch_bounds__(256) void head_kernel(
         float g = __builtin_fmaf(g0, (float)W3[i], g1 * (float)W3[h2 + i]);
         if (!(Z2[b * h2 + i] > 0.0f)) g = 0.0f;
         dz2[b * h2 + i] = g;
-        dz2_16[b * h2 + i] = (_Float16)g;
+        dz2_16[b * h2 + i] = half_of(g);
     }
 }
 
@@ -303,24 +314,42 @@ __global__ __launch_bounds__(256) void mean_kernel(const float* __restrict__ x, 
 
 // ----------------------------------------------------------------- fused inference
 // One workgroup per 64 LOS, hidden widths 256 and 256.  Thread t loads row
-// t / 4, inputs (t % 4) * 8 .. + 7 of every 32-wide K-chunk, one chunk ahead
-// of its use.  Pass 1 over the row accumulates sum (w Q)^2 + (w U)^2 (the
-// four threads of a row combine theirs by shuffles, a fixed order); pass 2
-// streams the same chunks again (mostly from L2/MALL), normalises and rounds
+// t / 4, inputs (t % 4) * 8 .. + 7 of every 32-wide K-chunk.  Pass 1 over the
+// row accumulates sum (w Q)^2 + (w U)^2 (the four threads of a row combine
+// theirs by shuffles, a fixed order); pass 2 streams the same chunks again
+// (mostly from L2/MALL) two chunks ahead of their use, normalises and rounds
 // them to half on their way into LDS, and feeds layer 1; layer 2 reads the
-// half h1 tile from LDS; the head reduces over lanes and waves.  Weights are
-// read from L2 straight into the B-operand registers.  No activation leaves
-// the CU.  VEC: nchan % 32 == 0 and 16-byte aligned rows, so every chunk lies
+// half h1 tile from LDS; the head reduces over lanes and waves.  Weights come
+// in MFMA-fragment order (frag16_kernel), so each fragment is one contiguous
+// 1 KB read per wave, two K-chunks ahead of its use.  No activation leaves
+// the CU.  Three workgroups share a CU (46 KB of LDS, at most 168 VGPRs
+// each), so that loads of one overlap the matrix work of the others.  VEC: nchan % 32 == 0 and 16-byte aligned rows, so every chunk lies
 // in Q or in U and loads as two float4.
 constexpr int FR = 64;                 // LOS per workgroup
 constexpr int FH = 256;                // hidden width
 constexpr int FHS = FH + 8;            // LDS row stride of h1 (halves)
 
+// Fragment order of an N x K half matrix W (row n at W + n ldw): fragment
+// (b, s) covers rows 32 b .. + 31 and columns 16 s .. + 15 and is 64 uint4,
+// lane l holding row 32 b + (l & 31), columns 16 s + 8 (l >> 5) .. + 7 (the
+// B operand of v_mfma_f32_32x32x16_f16), at out[(b K/16 + s) 64 + l].
+__global__ void frag16_kernel(const _Float16* __restrict__ W, int64_t N, int64_t K, int64_t ldw,
+                              uint4* __restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t ks = K / 16;
+    if (i >= (N / 32) * ks * 64) return;
+    const int l = (int)(i & 63);
+    const int64_t f = i >> 6, b = f / ks, sl = f - b * ks;
+    const int64_t n = 32 * b + (l & 31), k = 16 * sl + 8 * (l >> 5);
+    out[i] = *reinterpret_cast<const uint4*>(W + n * ldw + k);
+}
+
 template <bool VEC>
-__global__ __launch_bounds__(256, 2) void infer_fused_kernel(
+__global__ __launch_bounds__(256, 3) void infer_fused_kernel(
     const float* __restrict__ Q, const float* __restrict__ U, int64_t nlos, int nchan,
-    const float* __restrict__ w, int nin_pad, const _Float16* __restrict__ W1,
-    const float* __restrict__ b1, const _Float16* __restrict__ W2, const float* __restrict__ b2,
+    const float* __restrict__ w, int nin_pad, const uint4* __restrict__ W1f,
+    const float* __restrict__ b1, const uint4* __restrict__ W2f, const float* __restrict__ b2,
     const _Float16* __restrict__ W3, const float* __restrict__ b3, float phi_scale,
     float* __restrict__ phi_hat, float* __restrict__ score)
 {
@@ -336,54 +365,69 @@ __global__ __launch_bounds__(256, 2) void infer_fused_kernel(
     const float* qrow = Q + ll * nchan;
     const float* urow = U + ll * nchan;
     const int nin = 2 * nchan;
+    const int nch = nin_pad / GK;
 
     // The thread's 8 inputs of chunk k0 (raw data) and their channel weights.
-    auto load = [&](int k0, float (&v)[8], float (&wv)[8]) {
+    // VEC: nin is a multiple of 64, so nin_pad = nin and every chunk is data.
+    struct In {
+        float v[8], wv[8];
+    };
+    auto load = [&](int k0) -> In {
+        In x;
         if (VEC) {
-            const int k = k0 + lk;
-            if (k0 < nin) {
-                const float* src = k0 < nchan ? qrow + k : urow + (k - nchan);
-                const float* ws = w + (k0 < nchan ? k : k - nchan);
-                const float4 a = *reinterpret_cast<const float4*>(src);
-                const float4 b = *reinterpret_cast<const float4*>(src + 4);
-                const float4 c = *reinterpret_cast<const float4*>(ws);
-                const float4 d = *reinterpret_cast<const float4*>(ws + 4);
-                v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
-                v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
-                wv[0] = c.x; wv[1] = c.y; wv[2] = c.z; wv[3] = c.w;
-                wv[4] = d.x; wv[5] = d.y; wv[6] = d.z; wv[7] = d.w;
-            } else {
-#pragma unroll
-                for (int e = 0; e < 8; ++e) v[e] = wv[e] = 0.0f;
-            }
+            const bool inq = k0 < nchan;
+            const int j = (inq ? k0 : k0 - nchan) + lk;
+            const float* src = (inq ? qrow : urow) + j;
+            const float4 a = *reinterpret_cast<const float4*>(src);
+            const float4 b = *reinterpret_cast<const float4*>(src + 4);
+            const float4 c = *reinterpret_cast<const float4*>(w + j);
+            const float4 d = *reinterpret_cast<const float4*>(w + j + 4);
+            x.v[0] = a.x; x.v[1] = a.y; x.v[2] = a.z; x.v[3] = a.w;
+            x.v[4] = b.x; x.v[5] = b.y; x.v[6] = b.z; x.v[7] = b.w;
+            x.wv[0] = c.x; x.wv[1] = c.y; x.wv[2] = c.z; x.wv[3] = c.w;
+            x.wv[4] = d.x; x.wv[5] = d.y; x.wv[6] = d.z; x.wv[7] = d.w;
         } else {
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
                 const int k = k0 + lk + e;
                 const int j = k < nchan ? k : k - nchan;
                 const bool ok = k < nin;
-                v[e] = ok ? (k < nchan ? qrow[j] : urow[j]) : 0.0f;
-                wv[e] = ok ? w[j] : 0.0f;
+                x.v[e] = ok ? (k < nchan ? qrow[j] : urow[j]) : 0.0f;
+                x.wv[e] = ok ? w[j] : 0.0f;
             }
         }
+        return x;
     };
 
-    // Pass 1: sum of squares of the weighted inputs of the row.
+    // Pass 1: sum of squares of the weighted inputs of the row, chunks in
+    // order (three in flight).
     float ss = 0.0f;
     {
-        float v[8], wv[8], vn[8], wn[8];
-        load(0, v, wv);
-        for (int k0 = 0; k0 < nin_pad; k0 += GK) {
-            if (k0 + GK < nin_pad) load(k0 + GK, vn, wn);
+        int c = 0;
+        for (; c + 3 <= nch; c += 3) {
+            const In x0 = load(c * GK), x1 = load((c + 1) * GK), x2 = load((c + 2) * GK);
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
-                const float a = wv[e] == 0.0f ? 0.0f : wv[e] * v[e];
+                const float a = x0.wv[e] == 0.0f ? 0.0f : x0.wv[e] * x0.v[e];
                 ss = __builtin_fmaf(a, a, ss);
             }
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
-                v[e] = vn[e];
-                wv[e] = wn[e];
+                const float a = x1.wv[e] == 0.0f ? 0.0f : x1.wv[e] * x1.v[e];
+                ss = __builtin_fmaf(a, a, ss);
+            }
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const float a = x2.wv[e] == 0.0f ? 0.0f : x2.wv[e] * x2.v[e];
+                ss = __builtin_fmaf(a, a, ss);
+            }
+        }
+        for (; c < nch; ++c) {
+            const In x0 = load(c * GK);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const float a = x0.wv[e] == 0.0f ? 0.0f : x0.wv[e] * x0.v[e];
+                ss = __builtin_fmaf(a, a, ss);
             }
         }
     }
@@ -401,54 +445,64 @@ __global__ __launch_bounds__(256, 2) void infer_fused_kernel(
 #pragma unroll
             for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
 
-    // Pass 2: layer 1, chunk k0 contracted from sx[buf] while chunk k0 + 32 loads.
-    auto wfrag = [&](const _Float16* W, int ld, int k0, uint4 (&bv)[2][2]) {
+    // B fragments of K-chunk k0 (two 16-wide slices) for the wave's two
+    // 32-unit blocks.
+    auto wfrag = [&](const uint4* Wf, int ks, int k0, uint4 (&bv)[2][2]) {
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
-            for (int s = 0; s < 2; ++s)
-                bv[cb][s] = *reinterpret_cast<const uint4*>(
-                    W + (int64_t)(ncol + 32 * cb + r) * ld + k0 + 16 * s + 8 * hsel);
+            for (int sl = 0; sl < 2; ++sl)
+                bv[cb][sl] = Wf[((int64_t)(2 * wave + cb) * ks + (k0 >> 4) + sl) * 64 + lane];
     };
-    auto stage = [&](int buf, const float (&v)[8], const float (&wv)[8]) {
+    auto copy = [](uint4 (&d)[2][2], const uint4 (&s)[2][2]) {
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+            for (int sl = 0; sl < 2; ++sl) d[cb][sl] = s[cb][sl];
+    };
+    auto stage = [&](int buf, const In& x) {
         f16x8_t xv;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) xv[e] = (_Float16)(wv[e] == 0.0f ? 0.0f : wv[e] * v[e] * inv);
+        for (int e = 0; e < 8; ++e)
+            xv[e] = half_of(x.wv[e] == 0.0f ? 0.0f : x.wv[e] * x.v[e] * inv);
         *reinterpret_cast<f16x8_t*>(&sx[buf][lrow][lk]) = xv;
     };
+    // Pass 2: layer 1.  Chunk c is contracted from sx[buf]; chunk c + 1 is
+    // already in registers and staged at the end; chunk c + 2 (data and
+    // weights) loads meanwhile.
+    const int ks1 = nin_pad / 16;
     {
-        float v[8], wv[8];
-        uint4 bv[2][2], bn[2][2];
-        load(0, v, wv);
-        stage(0, v, wv);
-        wfrag(W1, nin_pad, 0, bv);
+        In xn = load(0), xf;
+        uint4 bv[2][2], b1n[2][2], b2n[2][2];
+        stage(0, xn);
+        wfrag(W1f, ks1, 0, bv);
+        if (nch > 1) {
+            xn = load(GK);
+            wfrag(W1f, ks1, GK, b1n);
+        }
         __syncthreads();
         int buf = 0;
-        for (int k0 = 0; k0 < nin_pad; k0 += GK) {
-            const bool more = k0 + GK < nin_pad;
-            if (more) {
-                load(k0 + GK, v, wv);
-                wfrag(W1, nin_pad, k0 + GK, bn);
+        for (int c = 0; c < nch; ++c) {
+            if (c + 2 < nch) {
+                xf = load((c + 2) * GK);
+                wfrag(W1f, ks1, (c + 2) * GK, b2n);
             }
 #pragma unroll
-            for (int s = 0; s < 2; ++s) {
+            for (int sl = 0; sl < 2; ++sl) {
 #pragma unroll
                 for (int rb = 0; rb < 2; ++rb) {
-                    const uint4 a = *reinterpret_cast<const uint4*>(&sx[buf][32 * rb + r][16 * s + 8 * hsel]);
+                    const uint4 a = *reinterpret_cast<const uint4*>(&sx[buf][32 * rb + r][16 * sl + 8 * hsel]);
 #pragma unroll
                     for (int cb = 0; cb < 2; ++cb)
                         acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
-                            __builtin_bit_cast(f16x8_t, a), __builtin_bit_cast(f16x8_t, bv[cb][s]),
+                            __builtin_bit_cast(f16x8_t, a), __builtin_bit_cast(f16x8_t, bv[cb][sl]),
                             acc[rb][cb], 0, 0, 0);
                 }
             }
-            if (more) {
-                stage(buf ^ 1, v, wv);
-#pragma unroll
-                for (int cb = 0; cb < 2; ++cb)
-#pragma unroll
-                    for (int s = 0; s < 2; ++s) bv[cb][s] = bn[cb][s];
-            }
+            if (c + 1 < nch) stage(buf ^ 1, xn);
+            copy(bv, b1n);
+            copy(b1n, b2n);
+            xn = xf;
             __syncthreads();
             buf ^= 1;
         }
@@ -464,37 +518,35 @@ __global__ __launch_bounds__(256, 2) void infer_fused_kernel(
             for (int v = 0; v < 16; ++v) {
                 const int m = 32 * rb + 8 * (v >> 2) + 4 * hsel + (v & 3);
                 const float z = __builtin_fmaf(1.0f, acc[rb][cb][v], bn);
-                sh[m][n] = (_Float16)(z < 0.0f ? 0.0f : z);
+                sh[m][n] = half_of(z < 0.0f ? 0.0f : z);
                 acc[rb][cb][v] = 0.0f;
             }
     }
     __syncthreads();
 
-    // Layer 2 from the h1 tile, W2 fragments one chunk ahead.
+    // Layer 2 from the h1 tile, W2 fragments two chunks ahead.
     {
-        uint4 bv[2][2], bn[2][2];
-        wfrag(W2, FH, 0, bv);
-        for (int k0 = 0; k0 < FH; k0 += GK) {
-            const bool more = k0 + GK < FH;
-            if (more) wfrag(W2, FH, k0 + GK, bn);
+        constexpr int ks2 = FH / 16, nch2 = FH / GK;
+        uint4 bv[2][2], b1n[2][2], b2n[2][2];
+        wfrag(W2f, ks2, 0, bv);
+        wfrag(W2f, ks2, GK, b1n);
 #pragma unroll
-            for (int s = 0; s < 2; ++s) {
+        for (int c = 0; c < nch2; ++c) {
+            if (c + 2 < nch2) wfrag(W2f, ks2, (c + 2) * GK, b2n);
+#pragma unroll
+            for (int sl = 0; sl < 2; ++sl) {
 #pragma unroll
                 for (int rb = 0; rb < 2; ++rb) {
-                    const uint4 a = *reinterpret_cast<const uint4*>(&sh[32 * rb + r][k0 + 16 * s + 8 * hsel]);
+                    const uint4 a = *reinterpret_cast<const uint4*>(&sh[32 * rb + r][c * GK + 16 * sl + 8 * hsel]);
 #pragma unroll
                     for (int cb = 0; cb < 2; ++cb)
                         acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
-                            __builtin_bit_cast(f16x8_t, a), __builtin_bit_cast(f16x8_t, bv[cb][s]),
+                            __builtin_bit_cast(f16x8_t, a), __builtin_bit_cast(f16x8_t, bv[cb][sl]),
                             acc[rb][cb], 0, 0, 0);
                 }
             }
-            if (more) {
-#pragma unroll
-                for (int cb = 0; cb < 2; ++cb)
-#pragma unroll
-                    for (int s = 0; s < 2; ++s) bv[cb][s] = bn[cb][s];
-            }
+            copy(bv, b1n);
+            copy(b1n, b2n);
         }
     }
     // Head: h2 = relu(z2 + b2) rounded to half, dotted with the two rows of W3.
@@ -512,7 +564,7 @@ __global__ __launch_bounds__(256, 2) void infer_fused_kernel(
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
                 const float z = __builtin_fmaf(1.0f, acc[rb][cb][v], bn);
-                const float h = (float)(_Float16)(z < 0.0f ? 0.0f : z);
+                const float h = (float)half_of(z < 0.0f ? 0.0f : z);
                 p0[rb][v] = __builtin_fmaf(h, w0, p0[rb][v]);
                 p1[rb][v] = __builtin_fmaf(h, w1, p1[rb][v]);
             }
@@ -637,17 +689,32 @@ hipError_t mlp_launch_mean(const float* x, int64_t n, float* out, hipStream_t s)
 
 bool mlp_fused_supported(int h1, int h2, int nin_pad) { return h1 == FH && h2 == FH && nin_pad % GK == 0; }
 
-hipError_t mlp_launch_infer_fused(const float* Q, const float* U, int64_t nlos, int nchan,
-                                  const float* w, int nin_pad, const _Float16* W1, const float* b1,
-                                  const _Float16* W2, const float* b2, const _Float16* W3,
-                                  const float* b3, float phi_scale, float* phi_hat, float* score,
-                                  hipStream_t s)
+int64_t mlp_fused_frag_uint4(int nin_pad) { return (int64_t)FH * nin_pad / 8 + (int64_t)FH * FH / 8; }
+
+hipError_t mlp_launch_frag16(const _Float16* W1, const _Float16* W2, int nin_pad, uint4* frag,
+                             hipStream_t s)
 {
+    const int64_t n1 = (int64_t)FH * nin_pad / 8, n2 = (int64_t)FH * FH / 8;
+    hipLaunchKernelGGL(frag16_kernel, dim3(blocks_for(n1, 256)), dim3(256), 0, s, W1, (int64_t)FH,
+                       (int64_t)nin_pad, (int64_t)nin_pad, frag);
+    if (hipError_t e = hipGetLastError()) return e;
+    hipLaunchKernelGGL(frag16_kernel, dim3(blocks_for(n2, 256)), dim3(256), 0, s, W2, (int64_t)FH,
+                       (int64_t)FH, (int64_t)FH, frag + n1);
+    return hipGetLastError();
+}
+
+hipError_t mlp_launch_infer_fused(const float* Q, const float* U, int64_t nlos, int nchan,
+                                  const float* w, int nin_pad, const uint4* frag, const float* b1,
+                                  const float* b2, const _Float16* W3, const float* b3,
+                                  float phi_scale, float* phi_hat, float* score, hipStream_t s)
+{
+    const uint4* W1 = frag;
+    const uint4* W2 = frag + (int64_t)FH * nin_pad / 8;
     const int64_t blocks = (nlos + FR - 1) / FR;
     if (blocks <= 0) return hipSuccess;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-    const bool vec = nchan % GK == 0 && (uintptr_t)Q % 16 == 0 && (uintptr_t)U % 16 == 0 &&
-                     (uintptr_t)w % 16 == 0;
+    const bool vec = nchan % GK == 0 && nin_pad == 2 * nchan && (uintptr_t)Q % 16 == 0 &&
+                     (uintptr_t)U % 16 == 0 && (uintptr_t)w % 16 == 0;
     if (vec)
         hipLaunchKernelGGL(infer_fused_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, s, Q, U, nlos,
                            nchan, w, nin_pad, W1, b1, W2, b2, W3, b3, phi_scale, phi_hat, score);

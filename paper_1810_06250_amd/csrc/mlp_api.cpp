@@ -29,6 +29,8 @@ struct rmsynth_mlp_s {
     float* d_m = nullptr;
     float* d_v = nullptr;
     _Float16* d_w16 = nullptr;   // W1 | W2 | W3 as half
+    uint4* d_wfrag = nullptr;    // W1 | W2 as half in MFMA-fragment order (fused inference)
+    bool frag_stale = true;      // d_wfrag not yet rebuilt from the current half weights
     float* d_part = nullptr;     // partial sums of the column reductions
     // Activation buffers, rows = capacity (multiple of 64).
     int64_t cap_fwd = 0, cap_bwd = 0;
@@ -70,6 +72,7 @@ void free_mlp(rmsynth_mlp_s* m)
     free_acts(m);
     free_buf(m->d_chw); free_buf(m->d_p); free_buf(m->d_g); free_buf(m->d_m); free_buf(m->d_v);
     free_buf(m->d_w16);
+    free_buf(m->d_wfrag);
     free_buf(m->d_part);
     delete m;
 }
@@ -176,8 +179,12 @@ int gradient(rmsynth_mlp_s* m, const float* Q, const float* U, int64_t B, const 
     return RMSYNTH_OK;
 }
 
+// Half copies of the weights after every parameter change; the fragment-order
+// copy for fused inference is rebuilt lazily, by the next inference call on
+// its own stream (training steps do not need it).
 hipError_t refresh_half(rmsynth_mlp_s* m, hipStream_t s)
 {
+    m->frag_stale = true;
     return mlp_launch_weights16(m->d_p, m->nW1, m->h1, m->nW2, m->h2, m->nW3, m->d_w16, s);
 }
 
@@ -275,6 +282,8 @@ int create(int32_t nchan, int32_t h1, int32_t h2, const float* weights, float ph
         (e = hipMalloc(&m->d_p, pb)) != hipSuccess || (e = hipMalloc(&m->d_g, pb)) != hipSuccess ||
         (e = hipMalloc(&m->d_m, pb)) != hipSuccess || (e = hipMalloc(&m->d_v, pb)) != hipSuccess ||
         (e = hipMalloc(&m->d_w16, sizeof(_Float16) * (m->nW1 + m->nW2 + m->nW3))) != hipSuccess ||
+        (mlp_fused_supported(h1, h2, m->nin_pad) &&
+         (e = hipMalloc(&m->d_wfrag, sizeof(uint4) * mlp_fused_frag_uint4(m->nin_pad))) != hipSuccess) ||
         (e = hipMalloc(&m->d_part, sizeof(float) * mlp_reduce_part_floats(
                                        std::max<int64_t>(std::max(h1, h2), 2 * (int64_t)h2 + 2)))) != hipSuccess) {
         free_mlp(m);
@@ -415,10 +424,16 @@ int rmsynth_mlp_infer(rmsynth_mlp_t m, const float* Q, const float* U, int64_t n
     hipStream_t s = (hipStream_t)stream;
     if (mlp_fused_supported(m->h1, m->h2, m->nin_pad)) {
         // One pass over the cube, no activation buffers.
-        hipError_t e = mlp_launch_infer_fused(Q, U, nlos, m->nchan, m->d_chw, m->nin_pad, W1h(m),
-                                              m->d_p + m->off_b1(), W2h(m), m->d_p + m->off_b2(),
-                                              W3h(m), m->d_p + m->off_b3(), m->phi_scale, phi_hat,
-                                              score, s);
+        hipError_t e = hipSuccess;
+        if (m->frag_stale) {
+            e = mlp_launch_frag16(W1h(m), W2h(m), m->nin_pad, m->d_wfrag, s);
+            if (e != hipSuccess) return rms_hip_fail(e, "rmsynth_mlp_infer");
+            m->frag_stale = false;
+        }
+        e = mlp_launch_infer_fused(Q, U, nlos, m->nchan, m->d_chw, m->nin_pad,
+                                              m->d_wfrag, m->d_p + m->off_b1(),
+                                              m->d_p + m->off_b2(), W3h(m), m->d_p + m->off_b3(),
+                                              m->phi_scale, phi_hat, score, s);
         if (e != hipSuccess) return rms_hip_fail(e, "rmsynth_mlp_infer");
         return rms_ok();
     }
