@@ -173,6 +173,33 @@ def test_infer_matches_oracle_and_is_chunk_invariant(nchan, h1, h2):
     np.testing.assert_array_equal(host(sc2), sc[65_400:65_700])
 
 
+def test_infer_follows_parameter_changes():
+    """The fused kernel reads a fragment-order copy of W1 and W2 that the first
+    inference after a parameter change rebuilds: inference after set_params
+    and after an Adam step must use the new parameters."""
+    nchan, h1, h2, n = 288, 256, 256, 2048
+    w, Q, U, phi, det, p_a = _case(21, n, nchan, h1, h2)
+    _, _, _, _, _, p_b = _case(22, n, nchan, h1, h2)
+    net = rs.Mlp(nchan, h1, h2, weights=w, phi_scale=PHI_SCALE)
+    Qd, Ud = dev32(Q), dev32(U)
+    x = omlp.normalise(Q.astype(np.float64), U.astype(np.float64), w)
+
+    def check(p32):
+        ph, sc = (host(t) for t in net.infer(Qd, Ud))
+        o, _ = omlp.forward(_blocks(np.asarray(p32, np.float64), 2 * nchan, h1, h2), x, round16=True)
+        assert np.max(np.abs(ph / PHI_SCALE - o[:, 0]) / (1 + np.abs(o[:, 0]))) <= 2e-3
+        assert np.max(np.abs(sc - 1.0 / (1.0 + np.exp(-o[:, 1])))) <= 1e-3
+        return ph
+
+    net.set_params(p_a)
+    ph_a = check(p_a)
+    net.set_params(p_b)
+    ph_b = check(p_b)
+    assert not np.array_equal(ph_a, ph_b)
+    net.train_step(Qd, Ud, dev32(phi), dev32(det), lr=1e-2)
+    check(net.get_params())
+
+
 def test_nonfinite_inputs():
     nchan, h1, h2 = 32, 64, 64
     w = np.ones(nchan)
