@@ -57,7 +57,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c3")
-    ap.add_argument("--precision", default="bf16x3", choices=["bf16x3", "fp32"])
+    ap.add_argument("--precision", default="bf16x3", choices=["bf16x3", "fp16x3", "fp32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32-compare", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -386,7 +386,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16" if args.precision == "bf16x3" else "f32",
+        "dtype": {"bf16x3": "bf16", "fp16x3": "f16", "fp32": "f32"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {wl.nx}x{wl.ny} LOS, {nchan} channels "
                                f"{wl.f_lo:g}-{wl.f_hi:g} MHz, phi {wl.phi_lo:g}..{wl.phi_hi:g} "
