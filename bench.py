@@ -284,7 +284,8 @@ def gate_leg(rs, n_train):
     csel = csel.cpu().numpy()
     cmatch = np.zeros(nlos, bool)
     cmatch[csel] = cpk["idx"].cpu().numpy() == idx[csel]
-    # The judge against the FP64 oracle on a sample of detected lines of sight.
+    # The ungated search (the reference for the gate) against the FP64 oracle on a sample
+    # of detected lines of sight.
     sel = np.flatnonzero(det)[:512]
     Q64 = Q[torch.as_tensor(sel, device="cuda")].double().cpu().numpy()
     U64 = U[torch.as_tensor(sel, device="cuda")].double().cpu().numpy()

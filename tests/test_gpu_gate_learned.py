@@ -3,7 +3,7 @@
 the library's own kernels on spectra its own generator makes, its score
 threshold is calibrated on held-out lines of sight for 99.5 % recall, and the
 gated peak search on a c5-like cube is compared with the ungated search (the
-judge) and with the FP64 oracle.
+reference) and with the FP64 oracle.
 
 Training outcome is stochastic, so its figures are parity unpinned; what is
 pinned: gated lines of sight reproduce the ungated peaks bit for bit (same
@@ -85,7 +85,7 @@ def test_learned_gate_gains_over_ungated_search():
     assert match >= 0.99
     assert frac < 0.1
     assert t_gate < t_full
-    # The judge itself against the FP64 oracle, on detected lines of sight.
+    # The reference itself against the FP64 oracle, on detected lines of sight.
     sel = np.flatnonzero(det)[:256]
     Q64 = host(Q)[sel].astype(np.float64)
     U64 = host(U)[sel].astype(np.float64)
