@@ -330,20 +330,42 @@ __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
     const int half = lane >> 5, col = lane & 31;
     const int nc = n0 + 64 * wc + col;
     const bool full = (l0 + MT <= nlos) && (n0 + NT <= nphi);
+    if (FP16) {
+        // Undo the per-LOS scale 2^e: multiply by 2^-e, formed from the
+        // scale's exponent (exact; no division).  The lane's rows come in
+        // runs of four consecutive LOS, read as one float4 inside the cube
+        // when the scales are 16-byte aligned.
+        const bool vec_sc = ((uintptr_t)los_scale & 15) == 0;
+#pragma unroll
+        for (int g = 0; g < 2; ++g)
+#pragma unroll
+            for (int vq = 0; vq < 4; ++vq) {
+                const int64_t lb = l0 + 64 * wr + 32 * g + 8 * vq + 4 * half;
+                float sc[4];
+                if (vec_sc && lb + 3 < nlos) {
+                    const float4 s4 = *reinterpret_cast<const float4*>(los_scale + lb);
+                    sc[0] = s4.x; sc[1] = s4.y; sc[2] = s4.z; sc[3] = s4.w;
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) sc[e] = los_scale[lb + e < nlos ? lb + e : nlos - 1];
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const float inv = __builtin_ldexpf(1.0f, 1 - __builtin_amdgcn_frexp_expf(sc[e]));
+#pragma unroll
+                    for (int cb = 0; cb < 2; ++cb) {
+                        acc[g][0][cb][4 * vq + e] *= inv;
+                        acc[g][1][cb][4 * vq + e] *= inv;
+                    }
+                }
+            }
+    }
 #pragma unroll
     for (int g = 0; g < 2; ++g)
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
             const int i = 8 * (v >> 2) + 4 * half + (v & 3);
             const int64_t l = l0 + 64 * wr + 32 * g + i;
-            if (FP16) {
-                const float inv = 1.0f / los_scale[l < nlos ? l : nlos - 1];
-#pragma unroll
-                for (int cb = 0; cb < 2; ++cb) {
-                    acc[g][0][cb][v] *= inv;
-                    acc[g][1][cb][v] *= inv;
-                }
-            }
             const int64_t off = l * nphi + nc;
             float* fq = Fq + off;
             float* fu = Fu + off;
