@@ -251,11 +251,17 @@ def _full_size(name, prec_list, nsub):
         results[prec] = (err.max(), mism, bad)
         assert err.max() <= PREC_TOL[prec]
         assert mism == 0 and bad == 0
-        # The one-call transform + peaks gives the same peaks on the whole cube.
-        _, _, _, pk2 = plan.execute_peaks(cube["Q"], cube["U"], cube["layout"], PRECS[prec])
+        # The one-call transform + peaks gives the same peaks on the whole cube
+        # (written over the same Fq, Fu: no second output cube).
+        pk2 = {k: torch.empty_like(v) for k, v in pk.items()}
+        nb = rs.rmsynth_execute_peaks_workspace_size(plan.handle, wl.nlos, cube["layout"], PRECS[prec])
+        ws = torch.empty(nb, dtype=torch.uint8, device="cuda") if nb else None
+        rs.rmsynth_execute_peaks(plan.handle, cube["Q"], cube["U"], wl.nlos, cube["layout"],
+                                 PRECS[prec], Fq, Fu, None, pk2["idx"], pk2["phi_pk"], pk2["amp"],
+                                 pk2["q_pk"], pk2["u_pk"], ws, nb)
         for key in ("idx", "amp", "q_pk", "u_pk"):
             assert torch.equal(pk2[key], pk[key]), (name, prec, key)
-        del pk2
+        del pk2, ws
         torch.cuda.empty_cache()
     del Fq, Fu, cube
     torch.cuda.empty_cache()
