@@ -323,8 +323,9 @@ __global__ __launch_bounds__(256) void mean_kernel(const float* __restrict__ x, 
 // in MFMA-fragment order (frag16_kernel), so each fragment is one contiguous
 // 1 KB read per wave, two K-chunks ahead of its use.  No activation leaves
 // the CU.  Three workgroups share a CU (46 KB of LDS, at most 168 VGPRs
-// each), so that loads of one overlap the matrix work of the others.  VEC: nchan % 32 == 0 and 16-byte aligned rows, so every chunk lies
-// in Q or in U and loads as two float4.
+// each), so that loads of one overlap the matrix work of the others.
+// VEC: nchan % 32 == 0 (so nin_pad = 2 nchan) and 16-byte aligned rows, so
+// every chunk lies in Q or in U and loads as two float4.
 constexpr int FR = 64;                 // LOS per workgroup
 constexpr int FH = 256;                // hidden width
 constexpr int FHS = FH + 8;            // LDS row stride of h1 (halves)
