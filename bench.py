@@ -32,6 +32,30 @@ MFMA_FLOP_PER_SAMPLE = {"bf16x3": 24.0, "fp16x3": 24.0, "fp32": 8.0}
 HBM_PEAK_GBS = 8000.0
 METRIC = "LOS·chan·φ Gsamples/s + % MFMA peak, split-BF16 vs FP32 at ≤1e-5 rel err"
 
+# The paper's own measurements (Table 1), quoted as context with the hardware
+# it names (NVIDIA Tesla P100-SXM2-16GB against one thread of a vectorised CPU
+# code on an Intel Xeon E5-2690 v4): cube sizes (LOS, channels, phi) and the
+# seconds of the CPU run and of the GPU's compute phase (its FITS reorder and
+# the file I/O excluded).
+PAPER_TABLE1 = {
+    "WSRT-SINGS": {"los": 512 * 512, "chan": 803, "phi": 401, "cpu_s": 122.0, "gpu_compute_s": 8.0},
+    "LOFAR_LR": {"los": 540 * 540, "chan": 856, "phi": 7000, "cpu_s": 2370.0, "gpu_compute_s": 17.0},
+    "LOFAR_HR": {"los": 4000 * 4000, "chan": 856, "phi": 7000, "cpu_s": 208892.0,
+                 "gpu_compute_s": 827.0},
+}
+
+
+def paper_context():
+    out = {"source": "the paper's Table 1 (other hardware and cubes: context, not a target)",
+           "gpu": "NVIDIA Tesla P100-SXM2-16GB", "cpu": "Intel Xeon E5-2690 v4, 1 thread, vectorised"}
+    for name, r in PAPER_TABLE1.items():
+        n = r["los"] * r["chan"] * r["phi"]
+        out[name] = {"samples": n, "cpu_gsamples_s": n / r["cpu_s"] / 1e9,
+                     "gpu_compute_gsamples_s": n / r["gpu_compute_s"] / 1e9,
+                     "gpu_vs_cpu_compute": r["cpu_s"] / r["gpu_compute_s"]}
+    return out
+
+
 # HBM bytes per launch of the dominant kernel, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE counter runs scaled by a plain 1 GiB copy (FETCH x 2.0, WRITE x 1.0),
 # keyed by (workload, precision, sha256 prefix of the kernel source they were
@@ -413,6 +437,7 @@ def main():
         res["fp32_path"] = fp32
         res["speedup_vs_fp32_execute"] = fp32["execute_ms"] / ex_ms
         res["speedup_vs_fp32_step"] = fp32["ms_per_step"] / wall
+    res["paper_context"] = paper_context()
     if not args.no_cpu_baseline:
         sub = stratified_subsample(nlos, cube["src_los"], 4096, seed=wl.seed + 11)
         log("cpu_baseline: FP64 oracle on host cores")
