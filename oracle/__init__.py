@@ -13,6 +13,7 @@ from .oracle import (  # noqa: F401
     fdf,
     rmsf,
     peaks,
+    peak_angle,
     fdf_bruteforce,
     per_los_error,
     incoherent_scale,

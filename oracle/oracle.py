@@ -2,6 +2,7 @@
 
 * `fdf`, `rmsf`, `peaks`, `plan`, `plan_info`, `cost_flop` call the plain C
   triple loop in rmsynth_oracle.c (built by `build()` with gcc, no fast-math).
+* `peak_angle` is the polarization angle at the peak (eq. (14)), numpy FP64.
 * `fdf_bruteforce` is a second, independent evaluation of eq. (11) as a
   numpy complex128 matrix product, for tiny cubes.
 * `per_los_error` and `peak_agreement` are the comparison rules used by the
@@ -141,6 +142,18 @@ def peaks(Fq, Fu, phi):
                             _ptr(out["u_pk"]), _ptr(out["margin"])):
         raise ValueError("oracle_peaks failed")
     return out
+
+
+def peak_angle(q_pk, u_pk, phi_pk, lambda0_sq):
+    """Polarization angle of the peak referred to lambda^2 = 0 (eq. (14)):
+    half the phase of F(phi_pk) after undoing the exp(2i phi_pk lambda0^2)
+    that the lambda0^2 term of eq. (11) puts on it, in [0, pi) radians; NaN
+    where an input is not finite.  FP64, numpy."""
+    q, u, ph = _f64(q_pk), _f64(u_pk), _f64(phi_pk)
+    z = (q + 1j * u) * np.exp(-2j * ph * float(lambda0_sq))
+    chi = np.mod(0.5 * np.angle(z), np.pi)
+    bad = ~(np.isfinite(q) & np.isfinite(u) & np.isfinite(ph))
+    return np.where(bad, np.nan, chi)
 
 
 def fdf_bruteforce(Q, U, lambda2, w, phi, lambda0_sq=None):

@@ -72,6 +72,35 @@ def test_thin_source_shift_identity(oracle_mod):
     np.testing.assert_allclose(Fq[0] + 1j * Fu[0], expect, rtol=0, atol=1e-13)
 
 
+def test_peak_angle_recovers_the_screen_angle(oracle_mod):
+    """Eq. (14): for thin screens (eqs. (1), (3)) the angle at the peak,
+    referred to lambda^2 = 0, is the screen's intrinsic angle chi0 (mod pi),
+    whatever lambda0^2 the transform used, although the phase of F(phi_pk)
+    itself moves with lambda0^2."""
+    lam = band_lambda2(120.0, 168.0, 128)
+    w = np.ones(lam.size)
+    phi = np.arange(-100.0, 100.5, 1.0)
+    rng = np.random.default_rng(17)
+    n = 40
+    phi0 = phi[rng.integers(10, phi.size - 10, n)]
+    chi0 = rng.uniform(-2 * np.pi, 2 * np.pi, n)
+    P = thin_spectrum(lam, rng.uniform(0.01, 0.1, n), phi0, chi0)
+    phases = []
+    for l0 in (float("nan"), 0.0, 3.7):
+        Fq, Fu = oracle_mod.fdf(P.real, P.imag, lam, w, phi, lambda0_sq=l0)
+        pk = oracle_mod.peaks(Fq, Fu, phi)
+        np.testing.assert_array_equal(pk["phi_pk"], phi0)
+        used = oracle_mod.plan(lam, w)[1] if np.isnan(l0) else l0
+        chi = oracle_mod.peak_angle(pk["q_pk"], pk["u_pk"], pk["phi_pk"], used)
+        assert np.all((chi >= 0) & (chi < np.pi))
+        d = np.angle(np.exp(2j * (chi - chi0))) / 2
+        assert np.max(np.abs(d)) < 1e-12
+        phases.append(np.angle(pk["q_pk"] + 1j * pk["u_pk"]))
+    assert np.max(np.abs(np.angle(np.exp(1j * (phases[1] - phases[2]))))) > 0.1
+    nan = oracle_mod.peak_angle([np.nan, 1.0], [0.0, np.inf], [0.0, 1.0], 0.5)
+    assert np.all(np.isnan(nan))
+
+
 def test_off_grid_source_peaks_at_nearest_node(oracle_mod):
     """|R| is symmetric and falls monotonically on its main lobe, so a
     noise-free screen between grid nodes peaks at the nearest node."""
