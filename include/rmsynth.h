@@ -175,6 +175,19 @@ int rmsynth_peaks(rmsynth_plan_t plan, const float* Fq, const float* Fu, int64_t
                   int32_t* idx, float* phi_pk, float* amp, float* q_pk, float* u_pk,
                   void* stream);
 
+/*
+ * rmsynth_peak_angle -- polarization angle of each LOS's peak referred to
+ * lambda^2 = 0 (eq. (14), read as half the phase of F(phi_peak) after undoing
+ * the exp(2i phi_peak lambda0^2) the lambda0^2 term of eq. (11) puts on it;
+ * for a Faraday-thin screen it is the screen's intrinsic angle chi0).
+ *   phi_pk, q_pk, u_pk [nlos] device float, as written by rmsynth_peaks.
+ *   chi0     [nlos] device float (output): radians in [0, pi); NaN where an
+ *            input is not finite (LOS with idx = -1).
+ * Evaluated in FP64 from the FP32 inputs and the plan's lambda0^2.  nlos >= 0.
+ */
+int rmsynth_peak_angle(rmsynth_plan_t plan, const float* phi_pk, const float* q_pk,
+                       const float* u_pk, int64_t nlos, float* chi0, void* stream);
+
 /* rmsynth_destroy -- free a plan's device tables (NULL is a no-op).  The caller
  * must make sure no enqueued work still uses the plan. */
 void rmsynth_destroy(rmsynth_plan_t plan);

@@ -371,6 +371,19 @@ int rmsynth_peaks(rmsynth_plan_t p, const float* Fq, const float* Fu, int64_t nl
     return rms_ok();
 }
 
+int rmsynth_peak_angle(rmsynth_plan_t p, const float* phi_pk, const float* q_pk, const float* u_pk,
+                       int64_t nlos, float* chi0, void* stream)
+{
+    if (!p) return rms_fail(RMSYNTH_EINVAL, "rmsynth_peak_angle: plan is NULL");
+    if (nlos < 0) return rms_fail(RMSYNTH_EINVAL, "rmsynth_peak_angle: nlos=%lld", (long long)nlos);
+    if (nlos == 0) return rms_ok();
+    if (!phi_pk || !q_pk || !u_pk || !chi0) return rms_fail(RMSYNTH_EINVAL, "rmsynth_peak_angle: NULL buffer");
+    if (int rc = check_device(p)) return rc;
+    hipError_t e = launch_peak_angle(*p, phi_pk, q_pk, u_pk, nlos, chi0, (hipStream_t)stream);
+    if (e != hipSuccess) return rms_hip_fail(e, "rmsynth_peak_angle launch");
+    return rms_ok();
+}
+
 void rmsynth_destroy(rmsynth_plan_t p) { free_plan(p); }
 
 }  // extern "C"

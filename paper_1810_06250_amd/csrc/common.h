@@ -167,6 +167,8 @@ hipError_t launch_peaks(const rmsynth_plan_s& p, const float* Fq, const float* F
                         int32_t* idx, float* phi_pk, float* amp, float* q_pk, float* u_pk,
                         hipStream_t s);
 hipError_t launch_rmsf(const rmsynth_plan_s& p, float* re, float* im, hipStream_t s);
+hipError_t launch_peak_angle(const rmsynth_plan_s& p, const float* phi_pk, const float* q_pk,
+                             const float* u_pk, int64_t nlos, float* chi0, hipStream_t s);
 // Fused peaks of the factored kernels: records per LOS (one per half phi
 // tile), and the merge of the records into the rmsynth_peaks outputs.
 int factored_peak_parts(const rmsynth_plan_s& p);

@@ -96,7 +96,44 @@ __global__ __launch_bounds__(256) void rmsf_kernel(const double* __restrict__ bj
     im[k] = K * si;
 }
 
+// Polarization angle of each LOS's peak referred to lambda^2 = 0 (eq. (14)):
+// half the phase of F(phi_pk) de-rotated by exp(-2i phi_pk lambda0^2), taken
+// in FP64 from the FP32 peak values and wrapped to [0, pi).  NaN when an
+// input is not finite.
+__global__ void peak_angle_kernel(const float* __restrict__ phi_pk, const float* __restrict__ q_pk,
+                                  const float* __restrict__ u_pk, int64_t nlos, double lambda0_sq,
+                                  float* __restrict__ chi0)
+{
+    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= nlos) return;
+    const double q = q_pk[l], u = u_pk[l], ph = phi_pk[l];
+    if (!(__builtin_isfinite(q) && __builtin_isfinite(u) && __builtin_isfinite(ph))) {
+        chi0[l] = __builtin_nanf("");
+        return;
+    }
+    const double pi = 3.141592653589793;
+    double chi = 0.5 * atan2(u, q) - ph * lambda0_sq;
+    chi -= pi * floor(chi / pi);
+    // Rounding can leave chi = pi exactly; the interval is half-open.
+    float c = (float)chi;
+    chi0[l] = c < (float)pi ? c : 0.0f;
+}
+
 }  // namespace
+
+hipError_t launch_peak_angle(const rmsynth_plan_s& p, const float* phi_pk, const float* q_pk,
+                             const float* u_pk, int64_t nlos, float* chi0, hipStream_t s)
+{
+    for (int64_t l0 = 0; l0 < nlos;) {
+        const int64_t n = std::min<int64_t>(nlos - l0, (int64_t)kMaxBlocks * 256);
+        hipLaunchKernelGGL(peak_angle_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                           phi_pk + l0, q_pk + l0, u_pk + l0, n, p.lambda0_sq, chi0 + l0);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        l0 += n;
+    }
+    return hipSuccess;
+}
 
 hipError_t launch_peaks(const rmsynth_plan_s& p, const float* Fq, const float* Fu, int64_t nlos,
                         int32_t* idx, float* phi_pk, float* amp, float* q_pk, float* u_pk,

@@ -49,6 +49,7 @@ SIGNATURES = {
                                              _P, _P, _P, _SZ, _P]),
     "rmsynth_execute_peaks_workspace_size": (ctypes.c_int, [_P, _I64, _I32, _I32,
                                                             ctypes.POINTER(_SZ)]),
+    "rmsynth_peak_angle": (ctypes.c_int, [_P, _P, _P, _P, _I64, _P, _P]),
     "rmsynth_destroy": (None, [_P]),
     "rmsynth_last_error": (ctypes.c_char_p, []),
     "rmsynth_version": (ctypes.c_char_p, []),
@@ -182,6 +183,14 @@ def rmsynth_peaks(plan, Fq, Fu, nlos: int, idx, phi_pk=None, amp=None, q_pk=None
         plan, _dev(Fq, "Fq", f32), _dev(Fu, "Fu", f32), int(nlos), _dev(idx, "idx", torch.int32),
         _dev(phi_pk, "phi_pk", f32), _dev(amp, "amp", f32), _dev(q_pk, "q_pk", f32),
         _dev(u_pk, "u_pk", f32), _stream(stream)))
+
+
+def rmsynth_peak_angle(plan, phi_pk, q_pk, u_pk, nlos: int, chi0, stream=None):
+    import torch
+    f32 = torch.float32
+    _check("rmsynth_peak_angle", load_library().rmsynth_peak_angle(
+        plan, _dev(phi_pk, "phi_pk", f32), _dev(q_pk, "q_pk", f32), _dev(u_pk, "u_pk", f32),
+        int(nlos), _dev(chi0, "chi0", f32), _stream(stream)))
 
 
 def rmsynth_execute_peaks_workspace_size(plan, nlos: int, layout: int, precision: int) -> int:
@@ -400,6 +409,14 @@ class Plan:
         rmsynth_execute_peaks(self.handle, Q, U, nlos, layout, precision, Fq, Fu, Fa, out["idx"],
                               out["phi_pk"], out["amp"], out["q_pk"], out["u_pk"], ws, nb)
         return Fq, Fu, Fa, out
+
+    def peak_angle(self, pk):
+        """Polarization angle at each LOS's peak referred to lambda^2 = 0
+        (rmsynth_peak_angle) from a peaks dict (phi_pk, q_pk, u_pk)."""
+        import torch
+        chi = torch.empty_like(pk["phi_pk"])
+        rmsynth_peak_angle(self.handle, pk["phi_pk"], pk["q_pk"], pk["u_pk"], chi.shape[0], chi)
+        return chi
 
     def peaks(self, Fq, Fu):
         import torch

@@ -179,6 +179,40 @@ def test_thin_source_peak(prec):
 
 
 @pytest.mark.parametrize("prec", list(PRECS))
+def test_peak_angle(prec):
+    """rmsynth_peak_angle (eq. (14)) against the oracle's on the same FP32 peak
+    values, thin screens' intrinsic angles recovered, NaN for LOS without a
+    peak, and nlos = 0 a no-op."""
+    import torch
+    note(f"peak angle, {prec}")
+    wl = WORKLOADS["c3"]
+    lam, w, phi = wl.lambda2(), wl.weights(), wl.phi()
+    rng = np.random.default_rng(19)
+    n = 96
+    phi0 = phi[rng.integers(100, phi.size - 100, n)]
+    chi0 = rng.uniform(0, np.pi, n)
+    P = thin_spectrum(lam, rng.uniform(0.01, 0.1, n), phi0, chi0)
+    P[-1, 7] = np.nan                       # one LOS without a peak
+    plan = rs.Plan(lam, w, phi)
+    Fq, Fu, _ = plan.execute(dev32(P.real), dev32(P.imag), LOS_MAJOR, PRECS[prec])
+    pk = plan.peaks(Fq, Fu)
+    chi = host(plan.peak_angle(pk))
+    ref = oracle.peak_angle(host(pk["q_pk"]), host(pk["u_pk"]), host(pk["phi_pk"]),
+                            plan.info["lambda0_sq"])
+    assert np.isnan(chi[-1]) and np.isnan(ref[-1])
+    ok = slice(0, n - 1)
+    assert np.all((chi[ok] >= 0) & (chi[ok] < np.pi))
+    d = np.angle(np.exp(2j * (chi[ok].astype(np.float64) - ref[ok]))) / 2
+    assert np.max(np.abs(d)) < 1e-6, np.max(np.abs(d))
+    d0 = np.angle(np.exp(2j * (chi[ok].astype(np.float64) - chi0[ok]))) / 2
+    assert np.max(np.abs(d0)) < 2e-4, np.max(np.abs(d0))
+    empty = torch.full((4,), 7.0, device="cuda")
+    rs.rmsynth_peak_angle(plan.handle, empty, empty, empty, 0, empty)
+    torch.cuda.synchronize()
+    assert torch.all(empty == 7.0)
+
+
+@pytest.mark.parametrize("prec", list(PRECS))
 def test_linearity_and_determinism(prec):
     note(f"linearity/determinism, {prec}")
     c = make_small_cube(256, 128, 201, seed=21, nsrc=8)
