@@ -401,27 +401,21 @@ __global__ __launch_bounds__(256, 3) void infer_fused_kernel(
     };
 
     // Pass 1: sum of squares of the weighted inputs of the row, chunks in
-    // order (three in flight).
+    // order (six in flight: the accumulators are not live yet).
     float ss = 0.0f;
     {
         int c = 0;
-        for (; c + 3 <= nch; c += 3) {
-            const In x0 = load(c * GK), x1 = load((c + 1) * GK), x2 = load((c + 2) * GK);
+        for (; c + 6 <= nch; c += 6) {
+            In x[6];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const float a = x0.wv[e] == 0.0f ? 0.0f : x0.wv[e] * x0.v[e];
-                ss = __builtin_fmaf(a, a, ss);
-            }
+            for (int i = 0; i < 6; ++i) x[i] = load((c + i) * GK);
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const float a = x1.wv[e] == 0.0f ? 0.0f : x1.wv[e] * x1.v[e];
-                ss = __builtin_fmaf(a, a, ss);
-            }
+            for (int i = 0; i < 6; ++i)
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const float a = x2.wv[e] == 0.0f ? 0.0f : x2.wv[e] * x2.v[e];
-                ss = __builtin_fmaf(a, a, ss);
-            }
+                for (int e = 0; e < 8; ++e) {
+                    const float a = x[i].wv[e] == 0.0f ? 0.0f : x[i].wv[e] * x[i].v[e];
+                    ss = __builtin_fmaf(a, a, ss);
+                }
         }
         for (; c < nch; ++c) {
             const In x0 = load(c * GK);
