@@ -28,7 +28,8 @@ hipError_t mlp_launch_mean(const float* x, int64_t n, float* out, hipStream_t s)
 // Fused inference (hidden widths 256 and 256 only): phi_hat and score per LOS.
 // It reads W1 and W2 from a copy in MFMA-fragment order of
 // mlp_fused_frag_uint4(nin_pad) uint4, made from the half weights by
-// mlp_launch_frag16 (W1 [256][nin_pad], W2 [256][256]).
+// mlp_launch_frag16 (W1 [256][nin_pad], W2 [256][256]).  unit_w: every channel
+// weight is 1 (the weights are then not read).
 bool mlp_fused_supported(int h1, int h2, int nin_pad);
 int64_t mlp_fused_frag_uint4(int nin_pad);
 hipError_t mlp_launch_frag16(const _Float16* W1, const _Float16* W2, int nin_pad, uint4* frag,
@@ -36,7 +37,8 @@ hipError_t mlp_launch_frag16(const _Float16* W1, const _Float16* W2, int nin_pad
 hipError_t mlp_launch_infer_fused(const float* Q, const float* U, int64_t nlos, int nchan,
                                   const float* w, int nin_pad, const uint4* frag, const float* b1,
                                   const float* b2, const _Float16* W3, const float* b3,
-                                  float phi_scale, float* phi_hat, float* score, hipStream_t s);
+                                  float phi_scale, float* phi_hat, float* score, bool unit_w,
+                                  hipStream_t s);
 
 // Gate (gate.hip).  Compaction works on blocks of 1024 lines of sight:
 // counts needs gate_num_blocks(nlos) + 1 entries and ends holding the

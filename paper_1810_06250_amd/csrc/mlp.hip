@@ -325,7 +325,8 @@ __global__ __launch_bounds__(256) void mean_kernel(const float* __restrict__ x, 
 // the CU.  Three workgroups share a CU (46 KB of LDS, at most 168 VGPRs
 // each), so that loads of one overlap the matrix work of the others.
 // VEC: nchan % 32 == 0 (so nin_pad = 2 nchan) and 16-byte aligned rows, so
-// every chunk lies in Q or in U and loads as two float4.
+// every chunk lies in Q or in U and loads as two float4.  UNITW: every channel
+// weight is 1, so none are loaded.
 constexpr int FR = 64;                 // LOS per workgroup
 constexpr int FH = 256;                // hidden width
 constexpr int FHS = FH + 8;            // LDS row stride of h1 (halves)
@@ -346,7 +347,7 @@ __global__ void frag16_kernel(const _Float16* __restrict__ W, int64_t N, int64_t
     out[i] = *reinterpret_cast<const uint4*>(W + n * ldw + k);
 }
 
-template <bool VEC>
+template <bool VEC, bool UNITW>
 __global__ __launch_bounds__(256, 3) void infer_fused_kernel(
     const float* __restrict__ Q, const float* __restrict__ U, int64_t nlos, int nchan,
     const float* __restrict__ w, int nin_pad, const uint4* __restrict__ W1f,
@@ -381,8 +382,10 @@ __global__ __launch_bounds__(256, 3) void infer_fused_kernel(
             const float* src = (inq ? qrow : urow) + j;
             const float4 a = *reinterpret_cast<const float4*>(src);
             const float4 b = *reinterpret_cast<const float4*>(src + 4);
-            const float4 c = *reinterpret_cast<const float4*>(w + j);
-            const float4 d = *reinterpret_cast<const float4*>(w + j + 4);
+            const float4 c = UNITW ? make_float4(1.0f, 1.0f, 1.0f, 1.0f)
+                                   : *reinterpret_cast<const float4*>(w + j);
+            const float4 d = UNITW ? make_float4(1.0f, 1.0f, 1.0f, 1.0f)
+                                   : *reinterpret_cast<const float4*>(w + j + 4);
             x.v[0] = a.x; x.v[1] = a.y; x.v[2] = a.z; x.v[3] = a.w;
             x.v[4] = b.x; x.v[5] = b.y; x.v[6] = b.z; x.v[7] = b.w;
             x.wv[0] = c.x; x.wv[1] = c.y; x.wv[2] = c.z; x.wv[3] = c.w;
@@ -701,7 +704,8 @@ hipError_t mlp_launch_frag16(const _Float16* W1, const _Float16* W2, int nin_pad
 hipError_t mlp_launch_infer_fused(const float* Q, const float* U, int64_t nlos, int nchan,
                                   const float* w, int nin_pad, const uint4* frag, const float* b1,
                                   const float* b2, const _Float16* W3, const float* b3,
-                                  float phi_scale, float* phi_hat, float* score, hipStream_t s)
+                                  float phi_scale, float* phi_hat, float* score, bool unit_w,
+                                  hipStream_t s)
 {
     const uint4* W1 = frag;
     const uint4* W2 = frag + (int64_t)FH * nin_pad / 8;
@@ -711,10 +715,18 @@ hipError_t mlp_launch_infer_fused(const float* Q, const float* U, int64_t nlos, 
     const bool vec = nchan % GK == 0 && nin_pad == 2 * nchan && (uintptr_t)Q % 16 == 0 &&
                      (uintptr_t)U % 16 == 0 && (uintptr_t)w % 16 == 0;
     if (vec)
-        hipLaunchKernelGGL(infer_fused_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, s, Q, U, nlos,
-                           nchan, w, nin_pad, W1, b1, W2, b2, W3, b3, phi_scale, phi_hat, score);
+    {
+        if (unit_w)
+            hipLaunchKernelGGL((infer_fused_kernel<true, true>), dim3((unsigned)blocks), dim3(256), 0, s, Q,
+                               U, nlos, nchan, w, nin_pad, W1, b1, W2, b2, W3, b3, phi_scale, phi_hat,
+                               score);
+        else
+            hipLaunchKernelGGL((infer_fused_kernel<true, false>), dim3((unsigned)blocks), dim3(256), 0, s, Q,
+                               U, nlos, nchan, w, nin_pad, W1, b1, W2, b2, W3, b3, phi_scale, phi_hat,
+                               score);
+    }
     else
-        hipLaunchKernelGGL(infer_fused_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, s, Q, U,
+        hipLaunchKernelGGL((infer_fused_kernel<false, false>), dim3((unsigned)blocks), dim3(256), 0, s, Q, U,
                            nlos, nchan, w, nin_pad, W1, b1, W2, b2, W3, b3, phi_scale, phi_hat, score);
     return hipGetLastError();
 }

@@ -433,7 +433,10 @@ int rmsynth_mlp_infer(rmsynth_mlp_t m, const float* Q, const float* U, int64_t n
         e = mlp_launch_infer_fused(Q, U, nlos, m->nchan, m->d_chw, m->nin_pad,
                                               m->d_wfrag, m->d_p + m->off_b1(),
                                               m->d_p + m->off_b2(), W3h(m), m->d_p + m->off_b3(),
-                                              m->phi_scale, phi_hat, score, s);
+                                              m->phi_scale, phi_hat, score,
+                                              std::all_of(m->chan_w.begin(), m->chan_w.end(),
+                                                          [](float v) { return v == 1.0f; }),
+                                              s);
         if (e != hipSuccess) return rms_hip_fail(e, "rmsynth_mlp_infer");
         return rms_ok();
     }

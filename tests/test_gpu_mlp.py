@@ -173,6 +173,27 @@ def test_infer_matches_oracle_and_is_chunk_invariant(nchan, h1, h2):
     np.testing.assert_array_equal(host(sc2), sc[65_400:65_700])
 
 
+def test_infer_with_unit_weights_matches_oracle():
+    """All channel weights 1 (the fused kernel then reads none): against the
+    oracle, and equal to the network given the weights explicitly."""
+    nchan, h1, h2, n = 288, 256, 256, 3000
+    _, Q, U, _, _, p32 = _case(31, n, nchan, h1, h2)
+    w = np.ones(nchan)
+    a = rs.Mlp(nchan, h1, h2, phi_scale=PHI_SCALE)
+    b = rs.Mlp(nchan, h1, h2, weights=w, phi_scale=PHI_SCALE)
+    a.set_params(p32)
+    b.set_params(p32)
+    Qd, Ud = dev32(Q), dev32(U)
+    pa, sa = (host(t) for t in a.infer(Qd, Ud))
+    pb, sb = (host(t) for t in b.infer(Qd, Ud))
+    np.testing.assert_array_equal(pa, pb)
+    np.testing.assert_array_equal(sa, sb)
+    x = omlp.normalise(Q.astype(np.float64), U.astype(np.float64), w)
+    o, _ = omlp.forward(_blocks(p32.astype(np.float64), 2 * nchan, h1, h2), x, round16=True)
+    assert np.max(np.abs(pa / PHI_SCALE - o[:, 0]) / (1 + np.abs(o[:, 0]))) <= 2e-3
+    assert np.max(np.abs(sa - 1.0 / (1.0 + np.exp(-o[:, 1])))) <= 1e-3
+
+
 def test_infer_follows_parameter_changes():
     """The fused kernel reads a fragment-order copy of W1 and W2 that the first
     inference after a parameter change rebuilds: inference after set_params
