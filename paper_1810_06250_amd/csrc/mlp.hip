@@ -505,6 +505,11 @@ __global__ __launch_bounds__(256, 3) void infer_fused_kernel(
             buf ^= 1;
         }
     }
+    // The first two W2 chunks load while h1 is written.
+    constexpr int ks2 = FH / 16, nch2 = FH / GK;
+    uint4 w2a[2][2], w2b[2][2];
+    wfrag(W2f, ks2, 0, w2a);
+    wfrag(W2f, ks2, GK, w2b);
     // h1 = relu(z1 + b1) as half into LDS.
 #pragma unroll
     for (int cb = 0; cb < 2; ++cb) {
@@ -524,10 +529,9 @@ __global__ __launch_bounds__(256, 3) void infer_fused_kernel(
 
     // Layer 2 from the h1 tile, W2 fragments two chunks ahead.
     {
-        constexpr int ks2 = FH / 16, nch2 = FH / GK;
         uint4 bv[2][2], b1n[2][2], b2n[2][2];
-        wfrag(W2f, ks2, 0, bv);
-        wfrag(W2f, ks2, GK, b1n);
+        copy(bv, w2a);
+        copy(b1n, w2b);
 #pragma unroll
         for (int c = 0; c < nch2; ++c) {
             if (c + 2 < nch2) wfrag(W2f, ks2, (c + 2) * GK, b2n);
