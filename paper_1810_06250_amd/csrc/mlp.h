@@ -8,6 +8,14 @@ hipError_t mlp_launch_gemm(bool atr, bool btr, const _Float16* A, int64_t lda, c
                            int64_t ldb, int64_t M, int64_t N, int64_t K, float alpha,
                            const float* bias, bool relu, const float* mask, int64_t ldm, float* C32,
                            int64_t ldc, _Float16* C16, int64_t ldc16, hipStream_t s);
+// Weight gradient C[m][n] = alpha sum_k A[k][m] B[k][n] (both operands
+// K-major, the GEMM's transposed loads), split over K when M x N alone gives
+// too few workgroups; part holds part_floats floats of partial sums, at most
+// mlp_wgrad_part_floats(M N) are used.  Deterministic for a given K.
+int64_t mlp_wgrad_part_floats(int64_t max_mn);
+hipError_t mlp_launch_gemm_wgrad(const _Float16* A, int64_t lda, const _Float16* B, int64_t ldb,
+                                 int64_t M, int64_t N, int64_t K, float alpha, float* C, int64_t ldc,
+                                 float* part, int64_t part_floats, hipStream_t s);
 hipError_t mlp_launch_head(const _Float16* H2, const float* Z2, int h2, const _Float16* W3,
                            const float* b3, int64_t nvalid, int64_t nrows, float phi_scale,
                            const float* phi_label, const float* det_label, float* loss_b,

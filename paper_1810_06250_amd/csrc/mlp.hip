@@ -13,6 +13,8 @@
 // range; weight gradients are scaled by 1/batch in FP32.
 #include "mlp.h"
 
+#include <algorithm>
+
 namespace {
 
 // FP32 to half, the FP32 value rounded first: the empty asm keeps the
@@ -72,7 +74,12 @@ __global__ __launch_bounds__(256) void input_kernel(const float* __restrict__ Q,
 // one 32 x 32 block each), K-step 32 = two v_mfma_f32_32x32x16_f16.
 // Epilogue:  z = alpha acc + bias[n];  if mask: z = mask[m][n] > 0 ? z : 0;
 //            C32[m][n] = z;  C16[m][n] = relu ? max(z, 0) : z  (either NULL).
+// Split K (weight gradients, where M x N alone gives too few workgroups):
+// blockIdx.y of gridDim.y takes an even share of the K/32 steps and, with
+// part given, stores its raw sums to part[blockIdx.y][m][n] (plane = M N
+// floats each); reduce_split_kernel adds the planes in order.
 constexpr int GT = 64, GK = 32, GRS = GK + 8;  // LDS row stride in halves
+constexpr int64_t kMaxSplit = 16, kSplitCap = int64_t(1) << 22;  // split-K planes, floats
 
 template <bool TR>
 __device__ __forceinline__ void load_tile(const _Float16* __restrict__ P, int64_t ld, int64_t r0,
@@ -100,7 +107,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(
     const _Float16* __restrict__ A, int64_t lda, const _Float16* __restrict__ B, int64_t ldb,
     int64_t N, int64_t K, float alpha, const float* __restrict__ bias, int relu,
     const float* __restrict__ mask, int64_t ldm, float* __restrict__ C32, int64_t ldc,
-    _Float16* __restrict__ C16, int64_t ldc16)
+    _Float16* __restrict__ C16, int64_t ldc16, float* __restrict__ part, int64_t plane)
 {
     __shared__ _Float16 sa[GT][GRS];
     __shared__ _Float16 sb[GT][GRS];
@@ -112,15 +119,18 @@ __global__ __launch_bounds__(256) void gemm_kernel(
     f32x16_t acc;
 #pragma unroll
     for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+    const int64_t ks = K / GK;
+    const int64_t kb = (int64_t)blockIdx.y * ks / gridDim.y * GK;
+    const int64_t ke = (int64_t)(blockIdx.y + 1) * ks / gridDim.y * GK;
     uint4 av, bv;
-    load_tile<ATR>(A, lda, m0, 0, t, av);
-    load_tile<BTR>(B, ldb, n0, 0, t, bv);
-    for (int64_t k0 = 0; k0 < K; k0 += GK) {
+    load_tile<ATR>(A, lda, m0, kb, t, av);
+    load_tile<BTR>(B, ldb, n0, kb, t, bv);
+    for (int64_t k0 = kb; k0 < ke; k0 += GK) {
         __syncthreads();
         store_tile<ATR>(sa, t, av);
         store_tile<BTR>(sb, t, bv);
         __syncthreads();
-        if (k0 + GK < K) {
+        if (k0 + GK < ke) {
             load_tile<ATR>(A, lda, m0, k0 + GK, t, av);
             load_tile<BTR>(B, ldb, n0, k0 + GK, t, bv);
         }
@@ -135,6 +145,13 @@ __global__ __launch_bounds__(256) void gemm_kernel(
     }
     // D layout of the 32x32 block: column = lane % 32, row = 8(v/4) + 4(lane/32) + v%4.
     const int64_t n = n0 + 32 * wc + (lane & 31);
+    if (part) {
+        float* __restrict__ P = part + (int64_t)blockIdx.y * plane;
+#pragma unroll
+        for (int v = 0; v < 16; ++v)
+            P[(m0 + 32 * wr + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3)) * N + n] = acc[v];
+        return;
+    }
     const float bn = bias ? bias[n] : 0.0f;
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
@@ -269,6 +286,18 @@ __global__ void reduce_parts_kernel(const float* __restrict__ part, int64_t N, f
     for (int y = 0; y < RCH; ++y) s += part[y * N + n];
     if (out2 && n >= split) out2[n - split] = alpha * s;
     else out[n] = alpha * s;
+}
+
+// C[m][n] = alpha sum_y part[y][m][n] over the nsplit planes, in order.
+__global__ void reduce_split_kernel(const float* __restrict__ part, int nsplit, int64_t N,
+                                    int64_t plane, float alpha, float* __restrict__ C, int64_t ldc)
+{
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    const int64_t i = (int64_t)blockIdx.y * N + n;
+    float s = part[i];
+    for (int y = 1; y < nsplit; ++y) s += part[y * plane + i];
+    C[(int64_t)blockIdx.y * ldc + n] = alpha * s;
 }
 
 // Adam (Kingma & Ba, bias-corrected) on the FP32 master parameters.
@@ -622,12 +651,38 @@ hipError_t mlp_launch_gemm(bool atr, bool btr, const _Float16* A, int64_t lda, c
     const int r = relu ? 1 : 0;
 #define MLP_GEMM(a, b)                                                                           \
     hipLaunchKernelGGL((gemm_kernel<a, b>), dim3((unsigned)blocks), dim3(256), 0, s, A, lda, B,   \
-                       ldb, N, K, alpha, bias, r, mask, ldm, C32, ldc, C16, ldc16)
+                       ldb, N, K, alpha, bias, r, mask, ldm, C32, ldc, C16, ldc16, nullptr,      \
+                       (int64_t)0)
     if (!atr && !btr) MLP_GEMM(false, false);
     else if (!atr && btr) MLP_GEMM(false, true);
     else if (atr && btr) MLP_GEMM(true, true);
     else MLP_GEMM(true, false);
 #undef MLP_GEMM
+    return hipGetLastError();
+}
+
+int64_t mlp_wgrad_part_floats(int64_t max_mn) { return std::min<int64_t>(kMaxSplit * max_mn, kSplitCap); }
+
+hipError_t mlp_launch_gemm_wgrad(const _Float16* A, int64_t lda, const _Float16* B, int64_t ldb,
+                                 int64_t M, int64_t N, int64_t K, float alpha, float* C, int64_t ldc,
+                                 float* part, int64_t part_floats, hipStream_t s)
+{
+    if (M <= 0 || N <= 0 || K <= 0 || M % GT || N % GT || K % GK || lda % 8 || ldb % 8)
+        return hipErrorInvalidValue;
+    const int64_t blocks = (M / GT) * (N / GT), plane = M * N;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    // Enough workgroups to cover the chip twice, at least two K-steps each.
+    int64_t nsplit = std::min<int64_t>({kMaxSplit, (K / GK) / 2, (2 * 256 + blocks - 1) / blocks});
+    nsplit = std::min<int64_t>(nsplit, part ? part_floats / plane : 0);
+    if (nsplit <= 1)
+        return mlp_launch_gemm(true, true, A, lda, B, ldb, M, N, K, alpha, nullptr, false, nullptr, 0,
+                               C, ldc, nullptr, 0, s);
+    hipLaunchKernelGGL((gemm_kernel<true, true>), dim3((unsigned)blocks, (unsigned)nsplit), dim3(256),
+                       0, s, A, lda, B, ldb, N, K, 1.0f, nullptr, 0, nullptr, (int64_t)0, nullptr,
+                       (int64_t)0, nullptr, (int64_t)0, part, plane);
+    if (hipError_t e = hipGetLastError()) return e;
+    hipLaunchKernelGGL(reduce_split_kernel, dim3(blocks_for(N, 256), (unsigned)M), dim3(256), 0, s,
+                       part, (int)nsplit, N, plane, alpha, C, ldc);
     return hipGetLastError();
 }
 

@@ -32,6 +32,8 @@ struct rmsynth_mlp_s {
     uint4* d_wfrag = nullptr;    // W1 | W2 as half in MFMA-fragment order (fused inference)
     bool frag_stale = true;      // d_wfrag not yet rebuilt from the current half weights
     float* d_part = nullptr;     // partial sums of the column reductions
+    float* d_wpart = nullptr;    // split-K partial sums of the weight gradients
+    int64_t wpart_floats = 0;
     // Activation buffers, rows = capacity (multiple of 64).
     int64_t cap_fwd = 0, cap_bwd = 0;
     _Float16 *X = nullptr, *H1 = nullptr, *H2 = nullptr, *D2h = nullptr, *D1h = nullptr;
@@ -74,6 +76,7 @@ void free_mlp(rmsynth_mlp_s* m)
     free_buf(m->d_w16);
     free_buf(m->d_wfrag);
     free_buf(m->d_part);
+    free_buf(m->d_wpart);
     delete m;
 }
 
@@ -162,8 +165,8 @@ int gradient(rmsynth_mlp_s* m, const float* Q, const float* U, int64_t B, const 
                                   m->d_g + m->off_b3(), m->d_part, s);
     // gW2[o][i] = sum_b dz2[b][o] h1[b][i]
     if (e == hipSuccess)
-        e = mlp_launch_gemm(true, true, m->D2h, m->h2, m->H1, m->h1, m->h2, m->h1, rows, inv_b,
-                            nullptr, false, nullptr, 0, m->d_g + m->off_W2(), m->h1, nullptr, 0, s);
+        e = mlp_launch_gemm_wgrad(m->D2h, m->h2, m->H1, m->h1, m->h2, m->h1, rows, inv_b,
+                                  m->d_g + m->off_W2(), m->h1, m->d_wpart, m->wpart_floats, s);
     if (e == hipSuccess) e = mlp_launch_colsum(m->D2, B, m->h2, inv_b, m->d_g + m->off_b2(), m->d_part, s);
     // dz1[b][i] = (sum_o dz2[b][o] W2[o][i]) * (z1[b][i] > 0)
     if (e == hipSuccess)
@@ -171,8 +174,8 @@ int gradient(rmsynth_mlp_s* m, const float* Q, const float* U, int64_t B, const 
                             nullptr, false, m->Z1, m->h1, m->D1, m->h1, m->D1h, m->h1, s);
     // gW1[i][k] = sum_b dz1[b][i] x[b][k]
     if (e == hipSuccess)
-        e = mlp_launch_gemm(true, true, m->D1h, m->h1, m->X, m->nin_pad, m->h1, m->nin_pad, rows,
-                            inv_b, nullptr, false, nullptr, 0, m->d_g, m->nin_pad, nullptr, 0, s);
+        e = mlp_launch_gemm_wgrad(m->D1h, m->h1, m->X, m->nin_pad, m->h1, m->nin_pad, rows, inv_b,
+                                  m->d_g, m->nin_pad, m->d_wpart, m->wpart_floats, s);
     if (e == hipSuccess) e = mlp_launch_colsum(m->D1, B, m->h1, inv_b, m->d_g + m->off_b1(), m->d_part, s);
     if (e == hipSuccess && loss) e = mlp_launch_mean(m->lossb, B, loss, s);
     if (e != hipSuccess) return rms_hip_fail(e, who);
@@ -285,7 +288,9 @@ int create(int32_t nchan, int32_t h1, int32_t h2, const float* weights, float ph
         (mlp_fused_supported(h1, h2, m->nin_pad) &&
          (e = hipMalloc(&m->d_wfrag, sizeof(uint4) * mlp_fused_frag_uint4(m->nin_pad))) != hipSuccess) ||
         (e = hipMalloc(&m->d_part, sizeof(float) * mlp_reduce_part_floats(
-                                       std::max<int64_t>(std::max(h1, h2), 2 * (int64_t)h2 + 2)))) != hipSuccess) {
+                                       std::max<int64_t>(std::max(h1, h2), 2 * (int64_t)h2 + 2)))) != hipSuccess ||
+        (e = hipMalloc(&m->d_wpart, sizeof(float) * (m->wpart_floats = mlp_wgrad_part_floats(
+                                        std::max(m->nW1, m->nW2))))) != hipSuccess) {
         free_mlp(m);
         return rms_fail(RMSYNTH_ENOMEM, "%s: hipMalloc: %s", who, hipGetErrorString(e));
     }
