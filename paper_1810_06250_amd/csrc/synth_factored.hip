@@ -139,12 +139,15 @@ __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
     };
     Regs R0, R1, R2;
 
-    auto gload = [&](Regs& R, int ks) {
+    auto gload_rot = [&](Regs& R, int ks) {
+        const int j0 = ks * KC + 4 * hh;
+        R.rot[0] = bt[(j0 >> 1)];
+        R.rot[1] = bt[(j0 >> 1) + 1];
+    };
+    auto gload_vec = [&](Regs& R, int ks) {
         const int j0 = ks * KC + 4 * hh;
         R.th = Thi[(int64_t)ks * (NQ * NT) + t];
         R.tl = Tlo[(int64_t)ks * (NQ * NT) + t];
-        R.rot[0] = bt[(j0 >> 1)];
-        R.rot[1] = bt[(j0 >> 1) + 1];
         if (FAST) {
             if (LAYOUT == RMSYNTH_LOS_MAJOR) {
                 const float4 a = *reinterpret_cast<const float4*>(Q + lr * ld + j0);
@@ -168,6 +171,11 @@ __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
                 R.u[i] = ok ? U[at] : 0.0f;
             }
         }
+    };
+
+    auto gload = [&](Regs& R, int ks) {
+        gload_vec(R, ks);
+        gload_rot(R, ks);
     };
 
     // Channel i of the thread's 4: rotate, split.
@@ -262,10 +270,19 @@ __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
     };
 
     // Make the buffers written in this K-step visible to all waves: this
-    // wave's LDS reads and writes done, then the barrier.  Written out
-    // instead of __syncthreads(), whose release fence would also wait for
-    // the prefetch loads still in flight (they only fill registers).
-    auto sync_next = [&]() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); };
+    // wave's LDS reads and writes done (lgkmcnt(0), which also covers the
+    // scalar loads of the channel rotations issued just before), then the
+    // barrier.  Written out instead of __syncthreads(), whose release fence
+    // would also wait for the prefetch loads still in flight (they only fill
+    // registers); the empty asm statements keep the compiler from moving
+    // memory accesses across it, and as builtins the wait and the barrier
+    // stay visible to the compiler's own wait-count tracking.
+    auto sync_next = [&]() {
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0); vmcnt and expcnt unconstrained
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+    };
 
     // Three LDS buffers rotate: K-step k is contracted from buffer k % 3
     // while K-step k + 2 is packed into buffer (k + 2) % 3 (last read in step
@@ -273,14 +290,19 @@ __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
     // are read from buffer (k + 1) % 3 (complete since the previous barrier).
     // Three register sets rotate so that loads run two K-steps ahead of their
     // use: step k packs K-step k + 2 and loads K-step k + 4 into the set the
-    // previous step packed.  Load indices past the end are clamped to the
-    // last K-step (loaded, never stored).
+    // previous step packed (vector loads first; the scalar loads of the
+    // channel rotations last, just before the barrier, so that no wait for
+    // them holds up the step's first MFMAs: scalar loads return out of
+    // order, so any use of a scalar register waits for all of them).  Load
+    // indices past the end are clamped to the last K-step (loaded, never
+    // stored).
     Frag F;
     int bc = 0;  // buffer of K-step k; (bc + 1) % 3 and (bc + 2) % 3 follow
     auto step = [&](Regs& Rp, Regs& Rl, int k) {
         const int bf = bc == 2 ? 0 : bc + 1;
         const int bn = bf == 2 ? 0 : bf + 1;
-        gload(Rl, k + 4 < nk ? k + 4 : nk - 1);
+        const int kl = k + 4 < nk ? k + 4 : nk - 1;
+        gload_vec(Rl, kl);
         __builtin_amdgcn_sched_barrier(0);
         mma(abuf[bc], F, Rp);
         // Unconditional: past the last K-step these write a buffer nobody
@@ -294,6 +316,8 @@ __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
             __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
             __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);
         }
+        __builtin_amdgcn_sched_barrier(0);
+        gload_rot(Rl, kl);
         sync_next();
         bc = bf;
     };
