@@ -674,7 +674,7 @@ hipError_t mlp_launch_gemm_wgrad(const _Float16* A, int64_t lda, const _Float16*
     // Enough workgroups to cover the chip twice, at least two K-steps each.
     int64_t nsplit = std::min<int64_t>({kMaxSplit, (K / GK) / 2, (2 * 256 + blocks - 1) / blocks});
     nsplit = std::min<int64_t>(nsplit, part ? part_floats / plane : 0);
-    if (nsplit <= 1)
+    if (nsplit <= 1 || M > 65535)  // the reduction's grid has one row of workgroups per m
         return mlp_launch_gemm(true, true, A, lda, B, ldb, M, N, K, alpha, nullptr, false, nullptr, 0,
                                C, ldc, nullptr, 0, s);
     hipLaunchKernelGGL((gemm_kernel<true, true>), dim3((unsigned)blocks, (unsigned)nsplit), dim3(256),
