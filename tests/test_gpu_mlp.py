@@ -84,7 +84,10 @@ def _check_blocks(g_gpu, grads, nchan, h1, h2, what):
         assert np.max(np.abs(d)) <= 1e-2 * np.max(np.abs(b)) + 1e-12, (what, name)
 
 
-@pytest.mark.parametrize("B,nchan,h1,h2", [(200, 40, 64, 128), (64, 288, 256, 256), (1000, 33, 128, 64)])
+# (1024, 288, 256, 256) is the gate's training step: the weight-gradient GEMMs
+# split the batch into 15 uneven shares (gW1) and 16 (gW2).
+@pytest.mark.parametrize("B,nchan,h1,h2", [(200, 40, 64, 128), (64, 288, 256, 256), (1000, 33, 128, 64),
+                                          (1024, 288, 256, 256)])
 def test_gradient_matches_oracle(B, nchan, h1, h2):
     note(f"mlp grad B={B} nchan={nchan} h1={h1} h2={h2}")
     import torch
