@@ -56,6 +56,12 @@ int rmsynth_mlp_create(int32_t nchan, int32_t h1, int32_t h2, const float* weigh
 /* rmsynth_mlp_num_params -- length of the canonical parameter vector. */
 int rmsynth_mlp_num_params(rmsynth_mlp_t mlp, int64_t* nparams);
 
+/* rmsynth_mlp_info -- the sizes a network was created with (any pointer may
+ * be NULL): channels per spectrum, hidden widths, Faraday-depth scale of the
+ * first output.  Host only; EINVAL when mlp is NULL. */
+int rmsynth_mlp_info(rmsynth_mlp_t mlp, int32_t* nchan, int32_t* h1, int32_t* h2,
+                     float* phi_scale);
+
 /*
  * rmsynth_mlp_get_params / rmsynth_mlp_set_params -- copy the FP32 master
  * parameters to / from a HOST array of nparams floats in canonical order.

@@ -197,13 +197,17 @@ def per_los_error(Fq_gpu, Fu_gpu, Fq_ref, Fu_ref, floor=None):
 def peak_agreement(idx_gpu, Fq_ref, Fu_ref, ref_peaks, margin_thr=2e-5):
     """Peak-index rule.  Where the oracle's margin exceeds `margin_thr` the
     index must match exactly; elsewhere any index whose oracle |F| is within
-    (1 - margin_thr) of the maximum is accepted.  Returns
-    (n_unambiguous, n_mismatch_unambiguous, n_invalid_ambiguous)."""
+    (1 - margin_thr) of the maximum is accepted.  A LOS the oracle flags
+    (non-finite |F|, idx -1) must be flagged (-1) by the GPU too, and a LOS the
+    oracle does not flag must not be.  Returns
+    (n_unambiguous, n_mismatch_unambiguous, n_invalid_other), the last counting
+    ambiguous LOS with an unacceptable index and flag disagreements."""
     idx_gpu = np.asarray(idx_gpu).astype(np.int64)
-    unamb = ref_peaks["margin"] > margin_thr
+    flagged = np.asarray(ref_peaks["idx"]) < 0
+    unamb = (ref_peaks["margin"] > margin_thr) & ~flagged
     mism = int(np.sum(unamb & (idx_gpu != ref_peaks["idx"])))
-    amb = np.flatnonzero(~unamb)
-    bad = 0
+    bad = int(np.sum(flagged & (idx_gpu != -1)))
+    amb = np.flatnonzero(~unamb & ~flagged)
     for l in amb:
         k = idx_gpu[l]
         if k < 0 or k >= Fq_ref.shape[1]:

@@ -49,17 +49,20 @@ void free_plan(rmsynth_plan_s* p)
     delete p;
 }
 
-// A grid is treated as uniform when every phi_k lies within 1e-9 of the
-// grid's scale from phi_0 + k dphi, dphi = (phi_last - phi_0) / (nphi - 1).
-bool detect_uniform(const double* phi, int32_t nphi, double* phi0, double* dphi)
+// The factored kernels evaluate F at phi_0 + k dphi, dphi = (phi_last -
+// phi_0) / (nphi - 1), and report the caller's phi_k.  A grid is treated as
+// uniform when the phase this moves, 2 |phi_k - (phi_0 + k dphi)| |a_j| of
+// eq. (11), stays below kUniformPhaseTol radians for every k and every
+// channel of non-zero weight (amax = max_j |a_j| over those channels).
+constexpr double kUniformPhaseTol = 1e-8;
+
+bool detect_uniform(const double* phi, int32_t nphi, double amax, double* phi0, double* dphi)
 {
     *phi0 = phi[0];
     *dphi = nphi > 1 ? (phi[nphi - 1] - phi[0]) / (nphi - 1) : 0.0;
-    double scale = std::max(std::fabs(phi[0]), std::fabs(phi[nphi - 1]));
-    scale = std::max(scale, std::fabs(*dphi));
-    for (int32_t k = 0; k < nphi; ++k)
-        if (std::fabs(phi[k] - (*phi0 + k * *dphi)) > 1e-9 * std::max(scale, 1e-300)) return false;
-    return true;
+    double dev = 0.0;
+    for (int32_t k = 0; k < nphi; ++k) dev = std::max(dev, std::fabs(phi[k] - (*phi0 + k * *dphi)));
+    return 2.0 * dev * amax <= kUniformPhaseTol;
 }
 
 int build_factor_tables(rmsynth_plan_s* p)
@@ -170,7 +173,10 @@ int rmsynth_plan(const double* lambda2, const double* weights, int32_t nchan, co
         free_plan(p);
         return rms_hip_fail(e, "rmsynth_plan: hipMemcpy");
     }
-    p->uniform = detect_uniform(phi, nphi, &p->phi0, &p->dphi);
+    double amax = 0.0;
+    for (int32_t j = 0; j < nchan; ++j)
+        if (weights[j] > 0.0) amax = std::max(amax, std::fabs(lambda2[j] - p->lambda0_sq));
+    p->uniform = detect_uniform(phi, nphi, amax, &p->phi0, &p->dphi);
     if (p->uniform) {
         if (int rc = build_factor_tables(p)) {
             free_plan(p);
@@ -241,14 +247,15 @@ int check_execute_args(const rmsynth_plan_s* p, int64_t nlos, int32_t layout, in
     return RMSYNTH_OK;
 }
 
-// The transform in LOS batches (one grid stays below kMaxBlocks); with parts,
-// the factored kernels also write their per-tile peaks.
+// The transform in LOS batches (each grid within the dispatch limit, tiles of
+// at least 64 LOS of 256 threads); with parts, the factored kernels also
+// write their per-tile peaks.
 int run_execute(const rmsynth_plan_s* p, const float* Q, const float* U, int64_t nlos, int32_t layout,
                 int32_t precision, float* Fq, float* Fu, float* Fabs, float* scales, PeakPart* parts,
                 hipStream_t stream, const char* who)
 {
     const int64_t tiles_n = (p->nphi + 127) / 128;
-    const int64_t max_los = std::max<int64_t>(128, kMaxBlocks / tiles_n * 64);
+    const int64_t max_los = max_los_tiled(tiles_n, 64, 256);
     for (int64_t l0 = 0; l0 < nlos;) {
         const int64_t n = std::min(nlos - l0, max_los);
         ExecArgs a{};

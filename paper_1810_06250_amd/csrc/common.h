@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "launch_limits.h"
 #include "rmsynth.h"
 
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
@@ -175,10 +176,6 @@ int factored_peak_parts(const rmsynth_plan_s& p);
 hipError_t launch_peak_merge(const rmsynth_plan_s& p, const PeakPart* part, int64_t nlos,
                              const float* Fq, const float* Fu, int32_t* idx, float* phi_pk,
                              float* amp, float* q_pk, float* u_pk, hipStream_t s);
-
-// Largest number of workgroups one launch may use (grid x dimension limit,
-// kept well inside 2^31 - 1).
-constexpr int64_t kMaxBlocks = int64_t(1) << 30;
 
 inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 

@@ -144,7 +144,7 @@ hipError_t gate_launch_compact(const float* phi_hat, const float* score, int64_t
                                int32_t* counts, int64_t* list, hipStream_t s)
 {
     const int64_t nb = gate_num_blocks(nlos);
-    if (nb > 0x7fffffff) return hipErrorInvalidValue;
+    if (nb > max_blocks(256)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(gate_flag_kernel, dim3((unsigned)nb), dim3(256), 0, s, phi_hat, score, nlos,
                        tau, edge, gated, idx, amp, counts);
     if (hipError_t e = hipGetLastError()) return e;
@@ -158,6 +158,7 @@ hipError_t gate_launch_compact(const float* phi_hat, const float* score, int64_t
 hipError_t gate_launch_gather(const float* Q, const float* U, const int64_t* list, int64_t n,
                               int nchan, float* gQ, float* gU, hipStream_t s)
 {
+    if ((n + 3) / 4 > max_blocks(256)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(gather_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, Q, U, list, n,
                        nchan, gQ, gU);
     return hipGetLastError();
@@ -167,6 +168,7 @@ hipError_t gate_launch_scatter(const int64_t* list, int64_t n, const int32_t* gi
                                const float* gphi, const float* gamp, int32_t* idx, float* phi_pk,
                                float* amp, hipStream_t s)
 {
+    if ((n + 255) / 256 > max_blocks(256)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(scatter_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, list, n,
                        gidx, gphi, gamp, idx, phi_pk, amp);
     return hipGetLastError();

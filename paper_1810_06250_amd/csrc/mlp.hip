@@ -768,24 +768,32 @@ hipError_t mlp_launch_infer_fused(const float* Q, const float* U, int64_t nlos, 
 {
     const uint4* W1 = frag;
     const uint4* W2 = frag + (int64_t)FH * nin_pad / 8;
-    const int64_t blocks = (nlos + FR - 1) / FR;
-    if (blocks <= 0) return hipSuccess;
-    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    if (nlos <= 0) return hipSuccess;
     const bool vec = nchan % GK == 0 && nin_pad == 2 * nchan && (uintptr_t)Q % 16 == 0 &&
                      (uintptr_t)U % 16 == 0 && (uintptr_t)w % 16 == 0;
-    if (vec)
-    {
-        if (unit_w)
-            hipLaunchKernelGGL((infer_fused_kernel<true, true>), dim3((unsigned)blocks), dim3(256), 0, s, Q,
-                               U, nlos, nchan, w, nin_pad, W1, b1, W2, b2, W3, b3, phi_scale, phi_hat,
-                               score);
-        else
-            hipLaunchKernelGGL((infer_fused_kernel<true, false>), dim3((unsigned)blocks), dim3(256), 0, s, Q,
-                               U, nlos, nchan, w, nin_pad, W1, b1, W2, b2, W3, b3, phi_scale, phi_hat,
-                               score);
+    // Batches of whole 64-LOS workgroups within the grid limit (row offsets
+    // keep 16-byte alignment: nchan % GK == 0 on the vector path).
+    const int64_t max_los = max_items(FR, 256);
+    for (int64_t l0 = 0; l0 < nlos; l0 += max_los) {
+        const int64_t n = nlos - l0 < max_los ? nlos - l0 : max_los;
+        const int64_t blocks = (n + FR - 1) / FR;
+        const float* q = Q + l0 * nchan;
+        const float* u = U + l0 * nchan;
+        if (vec) {
+            if (unit_w)
+                hipLaunchKernelGGL((infer_fused_kernel<true, true>), dim3((unsigned)blocks), dim3(256), 0, s,
+                                   q, u, n, nchan, w, nin_pad, W1, b1, W2, b2, W3, b3, phi_scale,
+                                   phi_hat + l0, score + l0);
+            else
+                hipLaunchKernelGGL((infer_fused_kernel<true, false>), dim3((unsigned)blocks), dim3(256), 0,
+                                   s, q, u, n, nchan, w, nin_pad, W1, b1, W2, b2, W3, b3, phi_scale,
+                                   phi_hat + l0, score + l0);
+        } else {
+            hipLaunchKernelGGL((infer_fused_kernel<false, false>), dim3((unsigned)blocks), dim3(256), 0, s,
+                               q, u, n, nchan, w, nin_pad, W1, b1, W2, b2, W3, b3, phi_scale,
+                               phi_hat + l0, score + l0);
+        }
+        if (hipError_t e = hipGetLastError()) return e;
     }
-    else
-        hipLaunchKernelGGL((infer_fused_kernel<false, false>), dim3((unsigned)blocks), dim3(256), 0, s, Q, U,
-                           nlos, nchan, w, nin_pad, W1, b1, W2, b2, W3, b3, phi_scale, phi_hat, score);
-    return hipGetLastError();
+    return hipSuccess;
 }

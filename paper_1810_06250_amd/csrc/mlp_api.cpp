@@ -341,6 +341,16 @@ int rmsynth_mlp_num_params(rmsynth_mlp_t m, int64_t* nparams)
     return rms_ok();
 }
 
+int rmsynth_mlp_info(rmsynth_mlp_t m, int32_t* nchan, int32_t* h1, int32_t* h2, float* phi_scale)
+{
+    if (!m) return rms_fail(RMSYNTH_EINVAL, "rmsynth_mlp_info: network is NULL");
+    if (nchan) *nchan = m->nchan;
+    if (h1) *h1 = m->h1;
+    if (h2) *h2 = m->h2;
+    if (phi_scale) *phi_scale = m->phi_scale;
+    return rms_ok();
+}
+
 int rmsynth_mlp_get_params(rmsynth_mlp_t m, float* params)
 {
     if (!m || !params) return rms_fail(RMSYNTH_EINVAL, "rmsynth_mlp_get_params: NULL argument");
@@ -623,8 +633,8 @@ int rmsynth_synth_training(rmsynth_plan_t p, const rmsynth_train_spec* sp, uint6
     d.phi_lo = sp->phi_lo; d.phi_hi = sp->phi_hi;
     d.w_lo = sp->w_lo; d.w_hi = sp->w_hi;
     d.sigma = sp->sigma;
-    // Launch in batches that keep the grid within its limit.
-    const int64_t max_los = int64_t(1) << 30;
+    // Launch in batches that keep the grid within its limit (one wave per LOS).
+    const int64_t max_los = max_items(4, 256);
     for (int64_t l0 = 0; l0 < nlos; l0 += max_los) {
         const int64_t n = std::min(max_los, nlos - l0);
         e = train_launch_spectra(p->d_lambda2, p->nchan, d, seed, first_los + l0, n,

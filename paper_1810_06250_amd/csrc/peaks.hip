@@ -125,7 +125,7 @@ hipError_t launch_peak_angle(const rmsynth_plan_s& p, const float* phi_pk, const
                              const float* u_pk, int64_t nlos, float* chi0, hipStream_t s)
 {
     for (int64_t l0 = 0; l0 < nlos;) {
-        const int64_t n = std::min<int64_t>(nlos - l0, (int64_t)kMaxBlocks * 256);
+        const int64_t n = std::min<int64_t>(nlos - l0, max_items(256, 256));
         hipLaunchKernelGGL(peak_angle_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
                            phi_pk + l0, q_pk + l0, u_pk + l0, n, p.lambda0_sq, chi0 + l0);
         hipError_t e = hipGetLastError();
@@ -140,7 +140,7 @@ hipError_t launch_peaks(const rmsynth_plan_s& p, const float* Fq, const float* F
                         hipStream_t s)
 {
     for (int64_t l0 = 0; l0 < nlos;) {
-        const int64_t n = std::min<int64_t>(nlos - l0, kMaxBlocks * WAVES);
+        const int64_t n = std::min<int64_t>(nlos - l0, max_items(WAVES, 64 * WAVES));
         const int64_t blocks = (n + WAVES - 1) / WAVES;
         hipLaunchKernelGGL(peaks_kernel, dim3((unsigned)blocks), dim3(64 * WAVES), 0, s,
                            Fq + l0 * p.nphi, Fu + l0 * p.nphi, n, p.nphi, p.d_phi, idx + l0,

@@ -466,7 +466,7 @@ __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
 // earlier one, i.e. the lower phi index), then read Fq, Fu at the peak: the
 // same results as peaks_kernel on the stored outputs.
 __global__ void peak_merge_kernel(const PeakPart* __restrict__ part, int nparts, int64_t nlos,
-                                  int nphi, const double* __restrict__ phik,
+                                  int64_t part_ld, int nphi, const double* __restrict__ phik,
                                   const float* __restrict__ Fq, const float* __restrict__ Fu,
                                   int32_t* __restrict__ idx, float* __restrict__ phi_pk,
                                   float* __restrict__ amp, float* __restrict__ q_pk,
@@ -478,7 +478,7 @@ __global__ void peak_merge_kernel(const PeakPart* __restrict__ part, int nparts,
     int bi = -1;
     bool bad = false;
     for (int t = 0; t < nparts; ++t) {
-        const PeakPart p = part[t * nlos + l];
+        const PeakPart p = part[t * part_ld + l];
         bad |= p.idx == -2;
         if (p.m > best) {
             best = p.m;
@@ -661,8 +661,17 @@ hipError_t launch_peak_merge(const rmsynth_plan_s& p, const PeakPart* part, int6
                              const float* Fq, const float* Fu, int32_t* idx, float* phi_pk,
                              float* amp, float* q_pk, float* u_pk, hipStream_t s)
 {
-    if (nlos <= 0) return hipSuccess;
-    hipLaunchKernelGGL(peak_merge_kernel, dim3((unsigned)((nlos + 255) / 256)), dim3(256), 0, s, part,
-                       2 * p.ftiles, nlos, p.nphi, p.d_phi, Fq, Fu, idx, phi_pk, amp, q_pk, u_pk);
-    return hipGetLastError();
+    // Records are laid out [part][nlos]: a batch of LOS reads them with the
+    // full nlos as stride, through the part_ld argument.
+    for (int64_t l0 = 0; l0 < nlos;) {
+        const int64_t n = nlos - l0 < max_items(256, 256) ? nlos - l0 : max_items(256, 256);
+        hipLaunchKernelGGL(peak_merge_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                           part + l0, 2 * p.ftiles, n, nlos, p.nphi, p.d_phi, Fq + l0 * p.nphi,
+                           Fu + l0 * p.nphi, idx + l0, phi_pk ? phi_pk + l0 : nullptr,
+                           amp ? amp + l0 : nullptr, q_pk ? q_pk + l0 : nullptr,
+                           u_pk ? u_pk + l0 : nullptr);
+        if (hipError_t e = hipGetLastError()) return e;
+        l0 += n;
+    }
+    return hipSuccess;
 }

@@ -136,7 +136,7 @@ hipError_t train_launch_spectra(const double* lambda2, int nchan, const TrainSpe
                                 float* truth, hipStream_t st)
 {
     const int64_t blocks = (nlos + 3) / 4;
-    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    if (blocks > max_blocks(256)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(spectra_kernel, dim3((unsigned)blocks), dim3(256), 0, st, lambda2, nchan, s,
                        (uint32_t)seed, (uint32_t)(seed >> 32), first, nlos, Q, U, cls, truth);
     return hipGetLastError();
@@ -145,6 +145,7 @@ hipError_t train_launch_spectra(const double* lambda2, int nchan, const TrainSpe
 hipError_t train_launch_labels(const int32_t* idx, const float* phi_pk, const float* amp, int64_t n,
                                float thr, float* phi_label, float* det_label, hipStream_t st)
 {
+    if ((n + 255) / 256 > max_blocks(256)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(label_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, idx, phi_pk,
                        amp, n, thr, phi_label, det_label);
     return hipGetLastError();

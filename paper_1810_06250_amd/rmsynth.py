@@ -57,6 +57,8 @@ SIGNATURES = {
     "rmsynth_mlp_create": (ctypes.c_int, [_I32, _I32, _I32, _P, ctypes.c_float, ctypes.c_uint64,
                                           ctypes.POINTER(_P)]),
     "rmsynth_mlp_num_params": (ctypes.c_int, [_P, ctypes.POINTER(_I64)]),
+    "rmsynth_mlp_info": (ctypes.c_int, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32),
+                                        ctypes.POINTER(_I32), ctypes.POINTER(ctypes.c_float)]),
     "rmsynth_mlp_get_params": (ctypes.c_int, [_P, _P]),
     "rmsynth_mlp_set_params": (ctypes.c_int, [_P, _P]),
     "rmsynth_mlp_grad": (ctypes.c_int, [_P, _P, _P, _I64, _P, _P, _P, _P, _P]),
@@ -130,6 +132,52 @@ def _host64(a):
     return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
 
 
+# Size checks.  The C ABI takes bare pointers and cannot see how large a
+# buffer is, so every wrapper below checks the tensors it is given against
+# the sizes it passes (LOS, channels, phi) before anything is launched, and
+# raises ValueError on a mismatch.
+def _need(t, name, n):
+    """t (may be None) holds at least n elements."""
+    if t is not None and t.numel() < n:
+        raise ValueError(f"{name} has {t.numel()} elements, {n} needed")
+
+
+def _need_rows(t, name, nrows, ncols):
+    """t holds nrows x ncols elements; a 2-D t has rows of exactly ncols."""
+    if t is None:
+        return
+    if t.dim() == 2 and t.shape[1] != ncols:
+        raise ValueError(f"{name} has rows of {t.shape[1]}, expected {ncols}")
+    _need(t, name, nrows * ncols)
+
+
+def _need_cube(Q, U, nlos, nchan, layout):
+    """Q, U hold a cube of nlos LOS x nchan channels in the given layout."""
+    if Q is not None and U is not None and tuple(Q.shape) != tuple(U.shape):
+        raise ValueError(f"Q {tuple(Q.shape)} and U {tuple(U.shape)} differ in shape")
+    for t, name in ((Q, "Q"), (U, "U")):
+        if t is None:
+            continue
+        if layout == RMSYNTH_FREQ_MAJOR:
+            # channel planes of exactly nlos values (the plane stride is nlos)
+            if t.dim() == 2 and tuple(t.shape) != (nchan, nlos):
+                raise ValueError(f"{name} is {tuple(t.shape)}, frequency-major needs ({nchan}, {nlos})")
+            _need(t, name, nlos * nchan)
+        elif layout == RMSYNTH_LOS_MAJOR:
+            _need_rows(t, name, nlos, nchan)
+
+
+def _need_bytes(ws, nbytes):
+    if ws is not None and ws.numel() * ws.element_size() < nbytes:
+        raise ValueError(f"workspace has {ws.numel() * ws.element_size()} bytes, "
+                         f"workspace_bytes says {nbytes}")
+
+
+def _plan_dims(plan):
+    info = rmsynth_plan_info(plan)
+    return info["nchan"], info["nphi"]
+
+
 # ------------------------------------------------------------------ C-ABI names
 def rmsynth_plan(lambda2, weights, phi, lambda0_sq: float = float("nan")) -> ctypes.c_void_p:
     lam, w, ph = _host64(lambda2), _host64(weights), _host64(phi)
@@ -161,6 +209,9 @@ def rmsynth_workspace_size(plan, nlos: int, layout: int, precision: int) -> int:
 
 def rmsynth_rmsf(plan, R_re, R_im, stream=None):
     import torch
+    _, nphi = _plan_dims(plan)
+    _need(R_re, "R_re", nphi)
+    _need(R_im, "R_im", nphi)
     _check("rmsynth_rmsf", load_library().rmsynth_rmsf(
         plan, _dev(R_re, "R_re", torch.float32), _dev(R_im, "R_im", torch.float32), _stream(stream)))
 
@@ -168,6 +219,11 @@ def rmsynth_rmsf(plan, R_re, R_im, stream=None):
 def rmsynth_execute(plan, Q, U, nlos: int, layout: int, precision: int, Fq, Fu, Fabs=None,
                     workspace=None, workspace_bytes: int = 0, stream=None):
     import torch
+    nchan, nphi = _plan_dims(plan)
+    _need_cube(Q, U, int(nlos), nchan, layout)
+    for t, name in ((Fq, "Fq"), (Fu, "Fu"), (Fabs, "Fabs")):
+        _need_rows(t, name, int(nlos), nphi)
+    _need_bytes(workspace, int(workspace_bytes))
     f32 = torch.float32
     _check("rmsynth_execute", load_library().rmsynth_execute(
         plan, _dev(Q, "Q", f32), _dev(U, "U", f32), int(nlos), int(layout), int(precision),
@@ -178,6 +234,11 @@ def rmsynth_execute(plan, Q, U, nlos: int, layout: int, precision: int, Fq, Fu, 
 def rmsynth_peaks(plan, Fq, Fu, nlos: int, idx, phi_pk=None, amp=None, q_pk=None, u_pk=None,
                   stream=None):
     import torch
+    _, nphi = _plan_dims(plan)
+    _need_rows(Fq, "Fq", int(nlos), nphi)
+    _need_rows(Fu, "Fu", int(nlos), nphi)
+    for t, name in ((idx, "idx"), (phi_pk, "phi_pk"), (amp, "amp"), (q_pk, "q_pk"), (u_pk, "u_pk")):
+        _need(t, name, int(nlos))
     f32 = torch.float32
     _check("rmsynth_peaks", load_library().rmsynth_peaks(
         plan, _dev(Fq, "Fq", f32), _dev(Fu, "Fu", f32), int(nlos), _dev(idx, "idx", torch.int32),
@@ -187,6 +248,8 @@ def rmsynth_peaks(plan, Fq, Fu, nlos: int, idx, phi_pk=None, amp=None, q_pk=None
 
 def rmsynth_peak_angle(plan, phi_pk, q_pk, u_pk, nlos: int, chi0, stream=None):
     import torch
+    for t, name in ((phi_pk, "phi_pk"), (q_pk, "q_pk"), (u_pk, "u_pk"), (chi0, "chi0")):
+        _need(t, name, int(nlos))
     f32 = torch.float32
     _check("rmsynth_peak_angle", load_library().rmsynth_peak_angle(
         plan, _dev(phi_pk, "phi_pk", f32), _dev(q_pk, "q_pk", f32), _dev(u_pk, "u_pk", f32),
@@ -204,6 +267,13 @@ def rmsynth_execute_peaks(plan, Q, U, nlos: int, layout: int, precision: int, Fq
                           phi_pk=None, amp=None, q_pk=None, u_pk=None, workspace=None,
                           workspace_bytes: int = 0, stream=None):
     import torch
+    nchan, nphi = _plan_dims(plan)
+    _need_cube(Q, U, int(nlos), nchan, layout)
+    for t, name in ((Fq, "Fq"), (Fu, "Fu"), (Fabs, "Fabs")):
+        _need_rows(t, name, int(nlos), nphi)
+    for t, name in ((idx, "idx"), (phi_pk, "phi_pk"), (amp, "amp"), (q_pk, "q_pk"), (u_pk, "u_pk")):
+        _need(t, name, int(nlos))
+    _need_bytes(workspace, int(workspace_bytes))
     f32 = torch.float32
     _check("rmsynth_execute_peaks", load_library().rmsynth_execute_peaks(
         plan, _dev(Q, "Q", f32), _dev(U, "U", f32), int(nlos), int(layout), int(precision),
@@ -239,6 +309,21 @@ def rmsynth_mlp_create(nchan: int, h1: int, h2: int, weights=None, phi_scale: fl
     return h
 
 
+def rmsynth_mlp_info(mlp) -> dict:
+    nc, h1, h2 = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    ps = ctypes.c_float()
+    _check("rmsynth_mlp_info", load_library().rmsynth_mlp_info(
+        mlp, ctypes.byref(nc), ctypes.byref(h1), ctypes.byref(h2), ctypes.byref(ps)))
+    return dict(nchan=nc.value, h1=h1.value, h2=h2.value, phi_scale=ps.value)
+
+
+def _need_batch(mlp, Q, U, batch, phi_label, det_label):
+    nchan = rmsynth_mlp_info(mlp)["nchan"]
+    _need_cube(Q, U, batch, nchan, RMSYNTH_LOS_MAJOR)
+    _need(phi_label, "phi_label", batch)
+    _need(det_label, "det_label", batch)
+
+
 def rmsynth_mlp_num_params(mlp) -> int:
     n = ctypes.c_int64()
     _check("rmsynth_mlp_num_params", load_library().rmsynth_mlp_num_params(mlp, ctypes.byref(n)))
@@ -262,6 +347,9 @@ def rmsynth_mlp_set_params(mlp, params):
 
 def rmsynth_mlp_grad(mlp, Q, U, batch: int, phi_label, det_label, grad, loss=None, stream=None):
     import torch
+    _need_batch(mlp, Q, U, int(batch), phi_label, det_label)
+    _need(grad, "grad", rmsynth_mlp_num_params(mlp))
+    _need(loss, "loss", 1)
     f32 = torch.float32
     _check("rmsynth_mlp_grad", load_library().rmsynth_mlp_grad(
         mlp, _dev(Q, "Q", f32), _dev(U, "U", f32), int(batch), _dev(phi_label, "phi_label", f32),
@@ -272,6 +360,8 @@ def rmsynth_mlp_grad(mlp, Q, U, batch: int, phi_label, det_label, grad, loss=Non
 def rmsynth_mlp_train_step(mlp, Q, U, batch: int, phi_label, det_label, lr: float, loss=None,
                            stream=None):
     import torch
+    _need_batch(mlp, Q, U, int(batch), phi_label, det_label)
+    _need(loss, "loss", 1)
     f32 = torch.float32
     _check("rmsynth_mlp_train_step", load_library().rmsynth_mlp_train_step(
         mlp, _dev(Q, "Q", f32), _dev(U, "U", f32), int(batch), _dev(phi_label, "phi_label", f32),
@@ -280,6 +370,10 @@ def rmsynth_mlp_train_step(mlp, Q, U, batch: int, phi_label, det_label, lr: floa
 
 def rmsynth_mlp_infer(mlp, Q, U, nlos: int, phi_hat, score, stream=None):
     import torch
+    nchan = rmsynth_mlp_info(mlp)["nchan"]
+    _need_cube(Q, U, int(nlos), nchan, RMSYNTH_LOS_MAJOR)
+    _need(phi_hat, "phi_hat", int(nlos))
+    _need(score, "score", int(nlos))
     f32 = torch.float32
     _check("rmsynth_mlp_infer", load_library().rmsynth_mlp_infer(
         mlp, _dev(Q, "Q", f32), _dev(U, "U", f32), int(nlos), _dev(phi_hat, "phi_hat", f32),
@@ -296,6 +390,11 @@ def rmsynth_gate_workspace_size(plan, mlp, nlos: int) -> int:
 def rmsynth_gate_execute(plan, mlp, Q, U, nlos: int, tau: float, idx, phi_pk, amp, gated,
                          workspace, workspace_bytes: int, stream=None):
     import torch
+    nchan, _ = _plan_dims(plan)
+    _need_cube(Q, U, int(nlos), nchan, RMSYNTH_LOS_MAJOR)
+    for t, name in ((idx, "idx"), (phi_pk, "phi_pk"), (amp, "amp"), (gated, "gated")):
+        _need(t, name, int(nlos))
+    _need_bytes(workspace, int(workspace_bytes))
     f32, i32 = torch.float32, torch.int32
     _check("rmsynth_gate_execute", load_library().rmsynth_gate_execute(
         plan, mlp, _dev(Q, "Q", f32), _dev(U, "U", f32), int(nlos), float(tau),
@@ -325,6 +424,12 @@ def rmsynth_synth_training(plan, spec: TrainSpec, seed: int, first_los: int, nlo
                            phi_label=None, det_label=None, cls=None, truth=None, workspace=None,
                            workspace_bytes: int = 0, stream=None):
     import torch
+    nchan, _ = _plan_dims(plan)
+    _need_cube(Q, U, int(nlos), nchan, RMSYNTH_LOS_MAJOR)
+    for t, name in ((phi_label, "phi_label"), (det_label, "det_label"), (cls, "cls")):
+        _need(t, name, int(nlos))
+    _need(truth, "truth", 4 * int(nlos))
+    _need_bytes(workspace, int(workspace_bytes))
     f32 = torch.float32
     _check("rmsynth_synth_training", load_library().rmsynth_synth_training(
         plan, ctypes.byref(spec), int(seed) & (2**64 - 1), int(first_los), int(nlos),

@@ -44,3 +44,46 @@ def test_pins_catch_planted_mistake(tmp_path, name):
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-p", "no:cacheprovider",
                         "tests/test_oracle_pins.py"], cwd=tmp_path, capture_output=True, text=True)
     assert r.returncode != 0, f"pins did not catch mutant {name}:\n{r.stdout[-2000:]}"
+
+
+# Plausible mistakes in the comparison rules of oracle/oracle.py; each must make
+# tests/test_oracle_compare.py fail.
+PY_MUTANTS = {
+    "error_reduced_over_los": ("num = np.sqrt(dq * dq + du * du).max(axis=1)",
+                               "num = np.sqrt(dq * dq + du * du).max(axis=0)"),
+    "reference_reduced_over_los": ("den = np.hypot(Fq_ref, Fu_ref).max(axis=1)",
+                                   "den = np.hypot(Fq_ref, Fu_ref).max(axis=0)"),
+    "error_without_imaginary_part": ("num = np.sqrt(dq * dq + du * du)", "num = np.sqrt(dq * dq)"),
+    "floor_ignored": ("den = np.maximum(den, floor)", "den = den"),
+    "floor_replaces_reference": ("den = np.maximum(den, floor)", "den = floor"),
+    "floor_inverted": ("den = np.maximum(den, floor)", "den = np.minimum(den, floor)"),
+    "scale_unsquared_weights": ("P2 @ (w[keep] ** 2)", "P2 @ w[keep]"),
+    "scale_without_K": ("np.sqrt(P2 @ (w[keep] ** 2)) / w.sum()", "np.sqrt(P2 @ (w[keep] ** 2))"),
+    "scale_transposed_layout": ("if layout == 1:\n        Q, U = Q.T, U.T",
+                                "if layout == 0:\n        Q, U = Q.T, U.T"),
+    "ambiguity_mask_inverted": ('(ref_peaks["margin"] > margin_thr)', '(ref_peaks["margin"] <= margin_thr)'),
+    "margin_at_threshold_unambiguous": ('(ref_peaks["margin"] > margin_thr)',
+                                        '(ref_peaks["margin"] >= margin_thr)'),
+    "result_order_swapped": ("return int(unamb.sum()), mism, bad", "return mism, int(unamb.sum()), bad"),
+    "acceptance_band_ten_times_wider": ("(1.0 - margin_thr) * ref_peaks",
+                                        "(1.0 - 10.0 * margin_thr) * ref_peaks"),
+    "out_of_range_index_accepted": ("if k < 0 or k >= Fq_ref.shape[1]:", "if k < -1 or k > Fq_ref.shape[1]:"),
+    "flag_disagreement_ignored": ("bad = int(np.sum(flagged & (idx_gpu != -1)))", "bad = 0"),
+    "threshold_argument_ignored": ("def peak_agreement(idx_gpu, Fq_ref, Fu_ref, ref_peaks, margin_thr=2e-5):",
+                                   "def peak_agreement(idx_gpu, Fq_ref, Fu_ref, ref_peaks, margin_thr=2e-5):\n"
+                                   "    margin_thr = 2e-5"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(PY_MUTANTS))
+def test_comparison_pins_catch_planted_mistake(tmp_path, name):
+    src = open(os.path.join(ROOT, "oracle", "oracle.py")).read()
+    a, b = PY_MUTANTS[name]
+    assert src.count(a) == 1, f"mutation site for {name} not found exactly once"
+    for sub in ("tests", "synthetic", "oracle"):
+        shutil.copytree(os.path.join(ROOT, sub), tmp_path / sub,
+                        ignore=shutil.ignore_patterns("__pycache__", "test_oracle_mutants.py"))
+    (tmp_path / "oracle" / "oracle.py").write_text(src.replace(a, b))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-p", "no:cacheprovider",
+                        "tests/test_oracle_compare.py"], cwd=tmp_path, capture_output=True, text=True)
+    assert r.returncode != 0, f"comparison pins did not catch mutant {name}:\n{r.stdout[-2000:]}"
