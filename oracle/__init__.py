@@ -12,8 +12,11 @@ from .oracle import (  # noqa: F401
     threads,
     fdf,
     rmsf,
+    adjoint,
     peaks,
     peak_angle,
+    peak_fit,
+    peak_fit_from_spectra,
     fdf_bruteforce,
     per_los_error,
     incoherent_scale,

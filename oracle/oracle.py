@@ -57,6 +57,8 @@ def _load():
         lib.oracle_rmsf.restype = ctypes.c_int
         lib.oracle_peaks.argtypes = [P, P, i64, i32, P, P, P, P, P, P, P]
         lib.oracle_peaks.restype = ctypes.c_int
+        lib.oracle_adjoint.argtypes = [P, P, i64, P, i32, P, i32, d, P, P]
+        lib.oracle_adjoint.restype = ctypes.c_int
         lib.oracle_threads.argtypes = []
         lib.oracle_threads.restype = ctypes.c_int
         _lib = lib
@@ -119,6 +121,24 @@ def fdf(Q, U, lambda2, w, phi, layout=0, lambda0_sq=float("nan"), table_mode=Tru
     return Fq, Fu
 
 
+def adjoint(Cre, Cim, lambda2, w, phi, lambda0_sq=float("nan")):
+    """Spectrum of grid components C [nlos][nphi] (eq. (4) as a sum over the
+    grid, referred to lambda0^2): P = Pq + i Pu, each float64 [nlos][nchan].
+    w only fixes lambda0^2 (the weighted mean, unless lambda0_sq is given)."""
+    Cre, Cim = _f64(Cre), _f64(Cim)
+    lam, w, phi = _f64(lambda2), _f64(w), _f64(phi)
+    if Cre.ndim != 2 or Cre.shape[1] != phi.size or Cim.shape != Cre.shape:
+        raise ValueError("C must be [nlos][nphi]")
+    _, l0 = plan(lam, w, lambda0_sq)
+    nlos = Cre.shape[0]
+    Pq = np.empty((nlos, lam.size))
+    Pu = np.empty((nlos, lam.size))
+    if _load().oracle_adjoint(_ptr(Cre), _ptr(Cim), nlos, _ptr(phi), phi.size, _ptr(lam), lam.size,
+                              l0, _ptr(Pq), _ptr(Pu)):
+        raise ValueError("oracle_adjoint failed")
+    return Pq, Pu
+
+
 def rmsf(lambda2, w, phi, lambda0_sq=float("nan")):
     """R(phi) of eq. (12) as (re, im) float64 [nphi]."""
     lam, w, phi = _f64(lambda2), _f64(w), _f64(phi)
@@ -154,6 +174,52 @@ def peak_angle(q_pk, u_pk, phi_pk, lambda0_sq):
     chi = np.mod(0.5 * np.angle(z), np.pi)
     bad = ~(np.isfinite(q) & np.isfinite(u) & np.isfinite(ph))
     return np.where(bad, np.nan, chi)
+
+
+def peak_fit(amp_prev, amp_pk, amp_next, phi_prev, phi_pk, phi_next):
+    """Sub-grid peak of |F| (the paper gives phi_peak on the grid only; this
+    refinement is an extension): the vertex of the parabola through the three
+    points (phi_prev, amp_prev), (phi_pk, amp_pk), (phi_next, amp_next),
+    elementwise in FP64.  Returns (phi_fit, amp_fit).  Where a neighbour is
+    missing (NaN: the peak sits at an end of the grid) or the parabola does not
+    open downwards, the grid values are returned unchanged; where amp_pk or
+    phi_pk is NaN (no peak), both results are NaN."""
+    y0, y1, y2 = (np.asarray(a, np.float64) for a in (amp_prev, amp_pk, amp_next))
+    x0, x1, x2 = (np.asarray(a, np.float64) for a in (phi_prev, phi_pk, phi_next))
+    with np.errstate(divide="ignore", invalid="ignore"):
+        d0, d2 = x0 - x1, x2 - x1          # d0 < 0 < d2
+        # y(t) = y1 + B t + A t^2 through (d0, y0), (0, y1), (d2, y2), t = phi - phi_pk
+        s0, s2 = (y0 - y1) / d0, (y2 - y1) / d2
+        A = (s0 - s2) / (d0 - d2)
+        B = s0 - A * d0
+        t = -B / (2.0 * A)
+        top = y1 - B * B / (4.0 * A)
+    ok = np.isfinite(y0) & np.isfinite(y2) & np.isfinite(t) & (A < 0)
+    phi_fit = np.where(ok, x1 + t, x1)
+    amp_fit = np.where(ok, top, y1)
+    nopk = ~(np.isfinite(y1) & np.isfinite(x1))
+    return np.where(nopk, np.nan, phi_fit), np.where(nopk, np.nan, amp_fit)
+
+
+def peak_fit_from_spectra(Fq, Fu, phi, idx):
+    """peak_fit around the index idx[l] of each LOS of F (any precision):
+    |F| at idx - 1, idx, idx + 1 as FP64 hypot, neighbours past the grid ends
+    missing; idx = -1 gives NaN."""
+    Fq, Fu, phi = _f64(Fq), _f64(Fu), _f64(phi)
+    idx = np.asarray(idx, np.int64)
+    nlos, nphi = Fq.shape
+    rows = np.arange(nlos)
+    have = idx >= 0
+    k = np.where(have, idx, 0)
+
+    def amp_at(kk):
+        inside = have & (kk >= 0) & (kk < nphi)
+        kc = np.clip(kk, 0, nphi - 1)
+        return np.where(inside, np.hypot(Fq[rows, kc], Fu[rows, kc]), np.nan), \
+            np.where(inside, phi[kc], np.nan)
+
+    (y0, x0), (y1, x1), (y2, x2) = amp_at(k - 1), amp_at(k), amp_at(k + 1)
+    return peak_fit(y0, y1, y2, x0, x1, x2)
 
 
 def fdf_bruteforce(Q, U, lambda2, w, phi, lambda0_sq=None):

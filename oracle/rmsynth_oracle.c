@@ -155,6 +155,36 @@ int oracle_fdf(const double* Q, const double* U, int64_t nlos, int32_t layout,
     return 0;
 }
 
+/* eq. (4) with the integral over phi replaced by the sum over the grid: the
+ * spectrum of a Faraday dispersion function made of components C_k at the
+ * grid depths phi_k, referred to lambda0^2 as eq. (11) refers F,
+ *   P(lambda_j^2) = sum_k C_k exp(+2 i phi_k (lambda_j^2 - lambda0^2)),
+ * for every channel (weights play no part) and every line of sight.
+ * C: [nlos][nphi] (phi fastest); P: [nlos][nchan].  K w_j P_j is the adjoint
+ * of eq. (11) applied to C. */
+int oracle_adjoint(const double* Cre, const double* Cim, int64_t nlos, const double* phi,
+                   int32_t nphi, const double* lambda2, int32_t nchan, double lambda0_sq,
+                   double* Pre, double* Pim)
+{
+    if (nlos < 0 || nchan < 1 || nphi < 1) return -1;
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t l = 0; l < nlos; ++l) {
+        for (int32_t j = 0; j < nchan; ++j) {
+            double re = 0.0, im = 0.0;
+            for (int32_t k = 0; k < nphi; ++k) {
+                double theta = 2.0 * phi[k] * (lambda2[j] - lambda0_sq);
+                double c = cos(theta), s = sin(theta);
+                double x = Cre[(size_t)l * nphi + k], y = Cim[(size_t)l * nphi + k];
+                re += x * c - y * s;
+                im += y * c + x * s;
+            }
+            Pre[(size_t)l * nchan + j] = re;
+            Pim[(size_t)l * nchan + j] = im;
+        }
+    }
+    return 0;
+}
+
 /* eq. (12): the RMSF on the phi grid. */
 int oracle_rmsf(const double* lambda2, const double* w, int32_t nchan,
                 const double* phi, int32_t nphi, double K, double lambda0_sq,

@@ -24,6 +24,14 @@ MUTANTS = {
     "peak_tie_to_highest": ("if (a > m1) { m1 = a; best = k; }",
                             "if (a >= m1) { m1 = a; best = k; }"),
     "flagged_channels_used": ("if (!(w[j] > 0.0)) continue;          /* flagged channel */", ""),
+    "adjoint_conjugated": ("re += x * c - y * s;\n                im += y * c + x * s;",
+                           "re += x * c + y * s;\n                im += y * c - x * s;"),
+    "adjoint_without_lambda0": ("double theta = 2.0 * phi[k] * (lambda2[j] - lambda0_sq);\n                double c = cos(theta), s = sin(theta);",
+                                "double theta = 2.0 * phi[k] * lambda2[j];\n                double c = cos(theta), s = sin(theta);"),
+    "adjoint_missing_factor_2": ("double theta = 2.0 * phi[k] * (lambda2[j] - lambda0_sq);\n                double c = cos(theta), s = sin(theta);",
+                                 "double theta = phi[k] * (lambda2[j] - lambda0_sq);\n                double c = cos(theta), s = sin(theta);"),
+    "adjoint_parts_swapped": ("Pre[(size_t)l * nchan + j] = re;\n            Pim[(size_t)l * nchan + j] = im;",
+                              "Pre[(size_t)l * nchan + j] = im;\n            Pim[(size_t)l * nchan + j] = re;"),
     "cos_sin_swapped": ("c = ctab[(size_t)k * nchan + j];\n                    s = stab[(size_t)k * nchan + j];",
                         "s = ctab[(size_t)k * nchan + j];\n                    c = stab[(size_t)k * nchan + j];"),
 }
@@ -42,12 +50,14 @@ def test_pins_catch_planted_mistake(tmp_path, name):
                     str(tmp_path / "oracle" / "liboracle.so"),
                     str(tmp_path / "oracle" / "rmsynth_oracle.c"), "-lm"], check=True)
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-p", "no:cacheprovider",
-                        "tests/test_oracle_pins.py"], cwd=tmp_path, capture_output=True, text=True)
+                        "tests/test_oracle_pins.py", "tests/test_oracle_adjoint.py"], cwd=tmp_path,
+                       capture_output=True, text=True)
     assert r.returncode != 0, f"pins did not catch mutant {name}:\n{r.stdout[-2000:]}"
 
 
-# Plausible mistakes in the comparison rules of oracle/oracle.py; each must make
-# tests/test_oracle_compare.py fail.
+# Plausible mistakes in the comparison rules and the sub-grid peak of
+# oracle/oracle.py; each must make tests/test_oracle_compare.py or
+# tests/test_oracle_fit.py fail.
 PY_MUTANTS = {
     "error_reduced_over_los": ("num = np.sqrt(dq * dq + du * du).max(axis=1)",
                                "num = np.sqrt(dq * dq + du * du).max(axis=0)"),
@@ -69,6 +79,13 @@ PY_MUTANTS = {
                                         "(1.0 - 10.0 * margin_thr) * ref_peaks"),
     "out_of_range_index_accepted": ("if k < 0 or k >= Fq_ref.shape[1]:", "if k < -1 or k > Fq_ref.shape[1]:"),
     "flag_disagreement_ignored": ("bad = int(np.sum(flagged & (idx_gpu != -1)))", "bad = 0"),
+    "fit_offset_sign": ("t = -B / (2.0 * A)", "t = B / (2.0 * A)"),
+    "fit_neighbours_swapped": ("s0, s2 = (y0 - y1) / d0, (y2 - y1) / d2", "s0, s2 = (y2 - y1) / d0, (y0 - y1) / d2"),
+    "fit_top_without_correction": ("top = y1 - B * B / (4.0 * A)", "top = y1"),
+    "fit_on_squared_amplitude": ("np.where(inside, np.hypot(Fq[rows, kc], Fu[rows, kc]), np.nan)",
+                                 "np.where(inside, Fq[rows, kc] ** 2 + Fu[rows, kc] ** 2, np.nan)"),
+    "fit_edges_wrapped": ("inside = have & (kk >= 0) & (kk < nphi)\n        kc = np.clip(kk, 0, nphi - 1)",
+                          "inside = have\n        kc = kk % nphi"),
     "threshold_argument_ignored": ("def peak_agreement(idx_gpu, Fq_ref, Fu_ref, ref_peaks, margin_thr=2e-5):",
                                    "def peak_agreement(idx_gpu, Fq_ref, Fu_ref, ref_peaks, margin_thr=2e-5):\n"
                                    "    margin_thr = 2e-5"),
@@ -85,5 +102,5 @@ def test_comparison_pins_catch_planted_mistake(tmp_path, name):
                         ignore=shutil.ignore_patterns("__pycache__", "test_oracle_mutants.py"))
     (tmp_path / "oracle" / "oracle.py").write_text(src.replace(a, b))
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-p", "no:cacheprovider",
-                        "tests/test_oracle_compare.py"], cwd=tmp_path, capture_output=True, text=True)
+                        "tests/test_oracle_compare.py", "tests/test_oracle_fit.py"], cwd=tmp_path, capture_output=True, text=True)
     assert r.returncode != 0, f"comparison pins did not catch mutant {name}:\n{r.stdout[-2000:]}"
