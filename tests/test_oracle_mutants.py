@@ -104,3 +104,43 @@ def test_comparison_pins_catch_planted_mistake(tmp_path, name):
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-p", "no:cacheprovider",
                         "tests/test_oracle_compare.py", "tests/test_oracle_fit.py"], cwd=tmp_path, capture_output=True, text=True)
     assert r.returncode != 0, f"comparison pins did not catch mutant {name}:\n{r.stdout[-2000:]}"
+
+
+# Plausible mistakes in the RM-CLEAN and NUFFT oracles; each must make the
+# module's own pins fail.
+MOD_MUTANTS = {
+    "clean_gain_ignored": ("oracle/rmclean.py", "c = gain * r[p]", "c = r[p]", "tests/test_oracle_rmclean.py"),
+    "clean_rmsf_mirrored": ("oracle/rmclean.py", "r -= c * R2[(N - 1) + k - p]", "r -= c * R2[(N - 1) - k + p]",
+                            "tests/test_oracle_rmclean.py"),
+    "clean_component_not_accumulated": ("oracle/rmclean.py", "cc[l, p] += c", "cc[l, p] = c",
+                                        "tests/test_oracle_rmclean.py"),
+    "clean_stop_test_inclusive": ("oracle/rmclean.py", "if amp < cutoff:", "if amp <= cutoff:",
+                                  "tests/test_oracle_rmclean.py"),
+    "clean_restored_without_residual": ("oracle/rmclean.py", "restored = resid + cc @ beam.T",
+                                        "restored = cc @ beam.T", "tests/test_oracle_rmclean.py"),
+    "clean_beam_width_halved": ("oracle/rmclean.py", "(np.asarray(x, np.float64) / fwhm) ** 2",
+                                "(np.asarray(x, np.float64) / (0.5 * fwhm)) ** 2", "tests/test_oracle_rmclean.py"),
+    "nufft_phase_centre_dropped": ("oracle/nufft.py", "np.exp(-2j * a * phic)", "np.exp(-2j * a * 0.0)",
+                                   "tests/test_oracle_nufft.py"),
+    "nufft_no_deconvolution": ("oracle/nufft.py", "/ psi_hat(m, alpha, beta)[None, :]", "/ alpha",
+                               "tests/test_oracle_nufft.py"),
+    "nufft_non_periodic_distance": ("oracle/nufft.py",
+                                    "d = np.mod(xl[:, None] - x[None, :] + np.pi, 2.0 * np.pi) - np.pi",
+                                    "d = xl[:, None] - x[None, :]", "tests/test_oracle_nufft.py"),
+    "nufft_mode_sign": ("oracle/nufft.py", "G[:, np.mod(m, n)]", "G[:, np.mod(-m, n)]",
+                        "tests/test_oracle_nufft.py"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MOD_MUTANTS))
+def test_module_pins_catch_planted_mistake(tmp_path, name):
+    rel, a, b, tests = MOD_MUTANTS[name]
+    src = open(os.path.join(ROOT, rel)).read()
+    assert src.count(a) == 1, f"mutation site for {name} not found exactly once"
+    for sub in ("tests", "synthetic", "oracle"):
+        shutil.copytree(os.path.join(ROOT, sub), tmp_path / sub,
+                        ignore=shutil.ignore_patterns("__pycache__", "test_oracle_mutants.py"))
+    (tmp_path / rel).write_text(src.replace(a, b))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-p", "no:cacheprovider", tests],
+                       cwd=tmp_path, capture_output=True, text=True)
+    assert r.returncode != 0, f"pins did not catch mutant {name}:\n{r.stdout[-2000:]}"
