@@ -13,10 +13,11 @@ detection logit):
            BCE(sigmoid(o[1]), det) + det * (o[0] - phi / phi_scale)^2
 
 and Adam (Kingma & Ba 2015) updates FP32 master weights.  `round16`, when set,
-rounds to IEEE half precision at the points where the GPU kernels feed its
-16-bit matrix units (the inputs x and h of every layer and the weights), so
-that the two sides take identical precision decisions; all arithmetic here is
-FP64 otherwise.
+rounds the network's 16-bit inputs to IEEE half precision: the normalised
+spectrum x and the weight matrices (the survey's FP16 operands).  Values the
+network forms inside (h1, h2, the back-propagated dz) are never rounded here:
+`error_bound` gives, element by element, how far an evaluation that rounds
+them to half and accumulates in FP32 can move from this FP64 network.
 """
 from __future__ import annotations
 
@@ -45,12 +46,10 @@ def forward(params, x, round16=False):
     x16 = _r16(x, round16)
     z1 = x16 @ _r16(W1, round16).T + b1
     h1 = np.maximum(z1, 0.0)
-    h1_16 = _r16(h1, round16)
-    z2 = h1_16 @ _r16(W2, round16).T + b2
+    z2 = h1 @ _r16(W2, round16).T + b2
     h2 = np.maximum(z2, 0.0)
-    h2_16 = _r16(h2, round16)
-    o = h2_16 @ _r16(W3, round16).T + b3
-    cache = dict(x16=x16, z1=z1, h1_16=h1_16, z2=z2, h2_16=h2_16)
+    o = h2 @ _r16(W3, round16).T + b3
+    cache = dict(x16=x16, z1=z1, h1=h1, z2=z2, h2=h2)
     return o, cache
 
 
@@ -73,30 +72,111 @@ def loss_and_grad_out(o, phi_label, det_label, phi_scale):
     return loss, g
 
 
-def backward(params, cache, g_out, round16=False, dz_scale=1.0):
-    """Gradients of the mean loss w.r.t. (W1, b1, W2, b2, W3, b3).
-
-    With round16 the back-propagated dz are rounded to half as dz_scale * dz
-    (the GPU rounds the gradient of the batch sum, dz_scale = batch size) and
-    scaled back exactly afterwards."""
+def backward(params, cache, g_out, round16=False):
+    """Gradients of the mean loss w.r.t. (W1, b1, W2, b2, W3, b3); with
+    round16 the weight matrices enter as their half roundings (as in
+    `forward`)."""
     W1, b1, W2, b2, W3, b3 = (np.asarray(p, np.float64) for p in params)
-
-    def r16s(a):
-        return _r16(a * dz_scale, round16) / dz_scale if round16 else a
-
-    gW3 = g_out.T @ cache["h2_16"]
+    gW3 = g_out.T @ cache["h2"]
     gb3 = g_out.sum(axis=0)
     gh2 = g_out @ _r16(W3, round16)
     gz2 = gh2 * (cache["z2"] > 0)
-    gz2_16 = r16s(gz2)
-    gW2 = gz2_16.T @ cache["h1_16"]
+    gW2 = gz2.T @ cache["h1"]
     gb2 = gz2.sum(axis=0)
-    gh1 = gz2_16 @ _r16(W2, round16)
+    gh1 = gz2 @ _r16(W2, round16)
     gz1 = gh1 * (cache["z1"] > 0)
-    gz1_16 = r16s(gz1)
-    gW1 = gz1_16.T @ cache["x16"]
+    gW1 = gz1.T @ cache["x16"]
     gb1 = gz1.sum(axis=0)
     return [gW1, gb1, gW2, gb2, gW3, gb3]
+
+
+def error_bound(params, x, phi_label, det_label, phi_scale, u=2.0 ** -11, ua=2.0 ** -25,
+                acc=2.0 ** -24, lam=6.0):
+    """Elementwise error bar for the outputs o and mean-loss gradients of
+    `forward`/`backward` with round16 (x and the weights rounded to half)
+    against the same network evaluated with
+
+      * x, h1, h2 rounded to half from a value within FP32 accumulation
+        error (relative u, absolute ua below half's normal range),
+      * the back-propagated dz of both hidden layers rounded to half at the
+        scale of the batch-SUM gradient (relative u, absolute ua / batch),
+        the bias gradients summing the unrounded dz,
+      * every dot product accumulated in FP32 (relative acc per addition),
+      * ReLU masks taken from its own pre-activations (where |z| is within its
+        error bar the mask may differ, and the whole term it admits or
+        removes then counts as error).
+
+    Probabilistic rounding-error analysis (Higham & Mary, SIAM J. Sci.
+    Comput. 41, 2019): each rounding is an independent error uniform within
+    +-u|v| (variance u^2 v^2 / 3); the variances propagate through each
+    layer's products (a sum of independent errors adds their variances:
+    var(sum a_i e_i) = sum a_i^2 var(e_i)), ReLU is 1-Lipschitz, the sigmoid's
+    slope is at most 1/4; the bar is lam standard deviations.  A worst-case
+    bound (|A||B| in place of the squares) holds always but lies 100-300 times
+    above the errors a real evaluation makes, too far to be a useful bar.
+    Returns (bar on o [B][2], [bars on gW1, gb1, gW2, gb2, gW3, gb3])."""
+    W1, b1, W2, b2, W3, b3 = (np.asarray(p, np.float64) for p in params)
+    W1, W2, W3 = (_r16(W, True) for W in (W1, W2, W3))
+    q1, q2, q3 = W1 * W1, W2 * W2, W3 * W3
+    x16 = _r16(x, True)
+    B, nin = x16.shape
+    nh1, nh2 = W1.shape[0], W2.shape[0]
+    z1 = x16 @ W1.T + b1
+    h1 = np.maximum(z1, 0.0)
+    z2 = h1 @ W2.T + b2
+    h2 = np.maximum(z2, 0.0)
+    o = h2 @ W3.T + b3
+    r3 = u * u / 3.0          # variance of one half rounding, relative
+    a3 = acc * acc / 3.0      # variance of one FP32 rounding, relative
+
+    def rnd(v, var, absolute):                     # rounding of v to half
+        return var + r3 * v * v + absolute * absolute / 3.0
+
+    def accum(n, terms2):                          # n FP32 additions of terms with these squares
+        return a3 * n * terms2
+
+    v_x = rnd(x16, a3 * x16 * x16, ua)             # FP32 normalisation, then half
+    v_z1 = v_x @ q1.T + accum(nin + 1, (x16 * x16) @ q1.T + b1 * b1)
+    v_h1 = rnd(h1, v_z1, ua)
+    v_z2 = v_h1 @ q2.T + accum(nh1 + 1, (h1 * h1) @ q2.T + b2 * b2)
+    v_h2 = rnd(h2, v_z2, ua)
+    v_o = v_h2 @ q3.T + accum(nh2 + 1, (h2 * h2) @ q3.T + b3 * b3)
+
+    d = np.asarray(det_label, np.float64)
+    t = np.asarray(phi_label, np.float64) / phi_scale
+    s = o[:, 1]
+    ex = np.exp(-np.abs(s))
+    sig = np.where(s >= 0, 1.0 / (1.0 + ex), ex / (1.0 + ex))
+    g = np.stack([2.0 * d * (o[:, 0] - t), sig - d], axis=1) / B
+    g2 = g * g
+    v_g = np.stack([4.0 * d * v_o[:, 0] + a3 * 4 * (o[:, 0] ** 2 + t * t),
+                    v_o[:, 1] / 16.0 + a3 * 16], axis=1) / (B * B)
+
+    v_W3 = v_g.T @ (h2 * h2 + v_h2) + g2.T @ v_h2 + accum(B, g2.T @ (h2 * h2))
+    v_b3 = v_g.sum(axis=0) + accum(B, g2.sum(axis=0))
+
+    def hidden(gh, v_gh, z, v_z):                  # ReLU' mask, possibly flipped
+        m = z > 0
+        flip = np.abs(z) <= lam * np.sqrt(v_z)
+        gz = gh * m
+        v_gz = np.where(m, v_gh, 0.0) + np.where(flip, gh * gh + v_gh, 0.0)
+        return gz, v_gz
+
+    gh2 = g @ W3
+    v_gh2 = v_g @ q3 + accum(2, g2 @ q3)
+    gz2, v_gz2 = hidden(gh2, v_gh2, z2, v_z2)
+    v_gz2r = rnd(gz2, v_gz2, ua / B)
+    v_W2 = v_gz2r.T @ (h1 * h1 + v_h1) + (gz2 * gz2).T @ v_h1 + accum(B, (gz2 * gz2).T @ (h1 * h1))
+    v_b2 = v_gz2.sum(axis=0) + accum(B, (gz2 * gz2).sum(axis=0))
+
+    gh1 = gz2 @ W2
+    v_gh1 = v_gz2r @ q2 + accum(nh2, (gz2 * gz2) @ q2)
+    gz1, v_gz1 = hidden(gh1, v_gh1, z1, v_z1)
+    v_gz1r = rnd(gz1, v_gz1, ua / B)
+    v_W1 = v_gz1r.T @ (x16 * x16 + v_x) + (gz1 * gz1).T @ v_x + accum(B, (gz1 * gz1).T @ (x16 * x16))
+    v_b1 = v_gz1.sum(axis=0) + accum(B, (gz1 * gz1).sum(axis=0))
+    bar = [lam * np.sqrt(v) for v in (v_W1, v_b1, v_W2, v_b2, v_W3, v_b3)]
+    return lam * np.sqrt(v_o), bar
 
 
 def adam_update(params, grads, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):

@@ -1,13 +1,12 @@
 """Parity of the gate network's HIP kernels with the FP64 network oracle, and of
 the gated peak search with the ungated path, through the C ABI.
 
-The oracle mirrors the GPU's half-precision rounding points (round16, with the
-back-propagated dz rounded at the scale of the batch-sum gradient), so the
-remaining differences come from FP32 accumulation order and from the rare
-values whose FP32 and FP64 evaluations round to different halves (one half
-ulp, 2^-11 relative, on a small fraction of the entries), plus ReLU masks of
-pre-activations within that distance of zero.  Bars, per parameter block:
-||g_gpu - g_or||_2 <= 2e-3 ||g_or||_2 and max |g_gpu - g_or| <= 1e-2 max |g_or|.
+The reference is the FP64 network with its 16-bit inputs rounded to half (the
+normalised spectrum x and the weight matrices); nothing the kernels round
+inside (h1, h2, the back-propagated dz) is mirrored.  The bar is elementwise:
+|gpu - oracle| <= oracle.mlp.error_bound, the probabilistic rounding-error
+analysis of half rounding at those points plus FP32 accumulation (6 standard
+deviations, pinned on the CPU against the same arithmetic in numpy).
 """
 import os
 
@@ -66,22 +65,40 @@ def _case(seed, B, nchan, h1, h2, flagged=0.1):
 
 
 def _oracle_grad(p32, w, Q, U, phi, det, nchan, h1, h2, round16=True):
+    """Loss, gradients, outputs and the elementwise error bars of the FP64
+    network (round16: x and the weights rounded to half)."""
     params = _blocks(p32.astype(np.float64), 2 * nchan, h1, h2)
     x = omlp.normalise(Q.astype(np.float64), U.astype(np.float64), w)
     o, cache = omlp.forward(params, x, round16=round16)
     loss, g = omlp.loss_and_grad_out(o, phi.astype(np.float64), det.astype(np.float64), PHI_SCALE)
-    grads = omlp.backward(params, cache, g, round16=round16, dz_scale=float(len(Q)))
-    return loss, grads, o
+    grads = omlp.backward(params, cache, g, round16=round16)
+    e_o, bars = omlp.error_bound(params, x, phi.astype(np.float64), det.astype(np.float64),
+                                 PHI_SCALE)
+    # loss bar: first order in the output error (g is d loss / d o), the
+    # squared term of the phi loss, and the FP32 evaluation of the loss terms
+    loss_bar = float(np.sum(np.abs(g) * e_o) + np.mean(det * e_o[:, 0] ** 2) + 1e-5 * abs(loss))
+    return (loss, loss_bar), grads, o, bars
 
 
-def _check_blocks(g_gpu, grads, nchan, h1, h2, what):
+def _check_blocks(g_gpu, grads, bars, nchan, h1, h2, what):
     names = ["W1", "b1", "W2", "b2", "W3", "b3"]
-    for name, a, b in zip(names, _blocks(g_gpu, 2 * nchan, h1, h2), grads):
-        d = a - b
-        ref = np.linalg.norm(b)
+    for name, a, b, e in zip(names, _blocks(g_gpu, 2 * nchan, h1, h2), grads, bars):
         assert np.all(np.isfinite(a)), (what, name)
-        assert np.linalg.norm(d) <= 2e-3 * ref + 1e-12, (what, name, np.linalg.norm(d) / ref)
-        assert np.max(np.abs(d)) <= 1e-2 * np.max(np.abs(b)) + 1e-12, (what, name)
+        worst = np.max(np.abs(a - b) / np.maximum(e, 1e-300))
+        note(f"  {what} {name}: max |gpu - oracle| / bar = {worst:.3f}")
+        assert np.all(np.abs(a - b) <= e), (what, name, worst)
+
+
+def _check_outputs(ph, sc, params, x):
+    """phi_hat / phi_scale and sigmoid(logit) within the error bar of o
+    (the sigmoid's slope is at most 1/4; its FP32 evaluation adds < 1e-6)."""
+    o, _ = omlp.forward(params, x, round16=True)
+    e_o, _ = omlp.error_bound(params, x, np.zeros(len(x)), np.zeros(len(x)), PHI_SCALE)
+    sig = 1.0 / (1.0 + np.exp(-o[:, 1]))
+    assert np.all(np.abs(ph / PHI_SCALE - o[:, 0]) <= e_o[:, 0] + 1e-7 * np.abs(o[:, 0])), \
+        np.max(np.abs(ph / PHI_SCALE - o[:, 0]) / e_o[:, 0])
+    assert np.all(np.abs(sc - sig) <= 0.25 * e_o[:, 1] + 1e-6), \
+        np.max(np.abs(sc - sig) / (0.25 * e_o[:, 1] + 1e-6))
 
 
 # (1024, 288, 256, 256) is the gate's training step: the weight-gradient GEMMs
@@ -97,9 +114,9 @@ def test_gradient_matches_oracle(B, nchan, h1, h2):
     g, loss = net.grad(dev32(Q), dev32(U), dev32(phi), dev32(det))
     g = host(g).astype(np.float64)
     loss = float(host(loss)[0])
-    l_or, grads, _ = _oracle_grad(p32, w, Q, U, phi, det, nchan, h1, h2)
-    assert abs(loss - l_or) <= 1e-3 * abs(l_or), (loss, l_or)
-    _check_blocks(g, grads, nchan, h1, h2, "grad")
+    (l_or, l_bar), grads, _, bars = _oracle_grad(p32, w, Q, U, phi, det, nchan, h1, h2)
+    assert abs(loss - l_or) <= l_bar, (loss, l_or, l_bar)
+    _check_blocks(g, grads, bars, nchan, h1, h2, "grad")
     # Flagged channels feed nothing: their W1 columns get exactly zero gradient.
     gW1 = _blocks(g, 2 * nchan, h1, h2)[0]
     off = np.concatenate([w == 0, w == 0])
@@ -121,7 +138,7 @@ def test_gradient_of_unmirrored_oracle_is_close_too():
     net.set_params(p32)
     g, _ = net.grad(dev32(Q), dev32(U), dev32(phi), dev32(det))
     g = host(g).astype(np.float64)
-    _, grads, _ = _oracle_grad(p32, w, Q, U, phi, det, nchan, h1, h2, round16=False)
+    _, grads, _, _ = _oracle_grad(p32, w, Q, U, phi, det, nchan, h1, h2, round16=False)
     for a, b in zip(_blocks(g, 2 * nchan, h1, h2), grads):
         assert np.linalg.norm(a - b) <= 2e-2 * np.linalg.norm(b) + 1e-12
 
@@ -141,12 +158,15 @@ def test_adam_steps_match_oracle():
         note(f"adam step {step}")
         o, cache = omlp.forward(params, x, round16=True)
         _, g = omlp.loss_and_grad_out(o, phi.astype(np.float64), det.astype(np.float64), PHI_SCALE)
-        grads = omlp.backward(params, cache, g, round16=True, dz_scale=float(B))
+        grads = omlp.backward(params, cache, g, round16=True)
+        _, bars = omlp.error_bound(params, x, phi.astype(np.float64), det.astype(np.float64),
+                                   PHI_SCALE)
         omlp.adam_update(params, grads, m, v, step, lr)
         net.train_step(Qd, Ud, phid, detd, lr)
         p_gpu = net.get_params().astype(np.float64)
-        for a, b, gr in zip(_blocks(p_gpu, 2 * nchan, h1, h2), params, grads):
-            sure = np.abs(gr) > 1e-2 * np.max(np.abs(gr))   # gradient sign well determined
+        for a, b, gr, e in zip(_blocks(p_gpu, 2 * nchan, h1, h2), params, grads, bars):
+            # gradient sign certain (outside four error bars) and not tiny
+            sure = (np.abs(gr) > 4 * e) & (np.abs(gr) > 1e-2 * np.max(np.abs(gr)))
             assert np.max(np.abs(a - b)[sure], initial=0.0) <= 0.02 * lr * step
             assert np.max(np.abs(a - b)) <= 2.0 * lr * step + 1e-7
     # Flagged-channel weights never move.
@@ -170,10 +190,7 @@ def test_infer_matches_oracle_and_is_chunk_invariant(nchan, h1, h2):
     sel = np.r_[0:300, 65_400:65_700, n - 300:n]
     params = _blocks(p32.astype(np.float64), 2 * nchan, h1, h2)
     x = omlp.normalise(Q[sel].astype(np.float64), U[sel].astype(np.float64), w)
-    o, _ = omlp.forward(params, x, round16=True)
-    sig = 1.0 / (1.0 + np.exp(-o[:, 1]))
-    assert np.max(np.abs(ph[sel] / PHI_SCALE - o[:, 0]) / (1 + np.abs(o[:, 0]))) <= 2e-3
-    assert np.max(np.abs(sc[sel] - sig)) <= 1e-3
+    _check_outputs(ph[sel], sc[sel], params, x)
     # The same rows inferred alone give bit-identical outputs.
     ph2, sc2 = net.infer(Qd[65_400:65_700].contiguous(), Ud[65_400:65_700].contiguous())
     np.testing.assert_array_equal(host(ph2), ph[65_400:65_700])
@@ -196,9 +213,7 @@ def test_infer_with_unit_weights_matches_oracle():
     np.testing.assert_array_equal(pa, pb)
     np.testing.assert_array_equal(sa, sb)
     x = omlp.normalise(Q.astype(np.float64), U.astype(np.float64), w)
-    o, _ = omlp.forward(_blocks(p32.astype(np.float64), 2 * nchan, h1, h2), x, round16=True)
-    assert np.max(np.abs(pa / PHI_SCALE - o[:, 0]) / (1 + np.abs(o[:, 0]))) <= 2e-3
-    assert np.max(np.abs(sa - 1.0 / (1.0 + np.exp(-o[:, 1])))) <= 1e-3
+    _check_outputs(pa, sa, _blocks(p32.astype(np.float64), 2 * nchan, h1, h2), x)
 
 
 def test_infer_follows_parameter_changes():
@@ -214,9 +229,7 @@ def test_infer_follows_parameter_changes():
 
     def check(p32):
         ph, sc = (host(t) for t in net.infer(Qd, Ud))
-        o, _ = omlp.forward(_blocks(np.asarray(p32, np.float64), 2 * nchan, h1, h2), x, round16=True)
-        assert np.max(np.abs(ph / PHI_SCALE - o[:, 0]) / (1 + np.abs(o[:, 0]))) <= 2e-3
-        assert np.max(np.abs(sc - 1.0 / (1.0 + np.exp(-o[:, 1])))) <= 1e-3
+        _check_outputs(ph, sc, _blocks(np.asarray(p32, np.float64), 2 * nchan, h1, h2), x)
         return ph
 
     net.set_params(p_a)
@@ -326,9 +339,14 @@ def test_gate_argument_errors():
     f32 = torch.empty(10, dtype=torch.float32, device="cuda")
     nb = rs.rmsynth_gate_workspace_size(plan.handle, net.handle, 10)
     ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
-    with pytest.raises(rs.RmsynthError) as e:
+    # The binding refuses a cube that does not fit the plan before any call...
+    with pytest.raises(ValueError):
         rs.rmsynth_gate_execute(other.handle, net.handle, dev32(Q), dev32(U), 10, 0.5, i32, f32,
                                 f32, i32, ws, nb)
+    # ...and the library a plan whose channel count is not the network's.
+    with pytest.raises(rs.RmsynthError) as e:
+        rs.rmsynth_gate_execute(other.handle, net.handle, dev32(Q[:, :-1]), dev32(U[:, :-1]), 10,
+                                0.5, i32, f32, f32, i32, ws, nb)
     assert e.value.code == -1
     with pytest.raises(rs.RmsynthError) as e:
         rs.rmsynth_gate_execute(plan.handle, net.handle, dev32(Q), dev32(U), 10, 0.5, i32, f32,

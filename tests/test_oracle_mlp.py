@@ -87,23 +87,80 @@ def test_relu_network_forward_by_hand():
     np.testing.assert_allclose(o, [[3.75, -7.0], [0.25, 0.0]], rtol=0, atol=1e-15)
 
 
-def test_dz_scale_only_moves_the_half_rounding_point():
-    """Without half rounding dz_scale has no effect; with it, a power-of-two
-    scale leaves every rounding decision unchanged (half rounding commutes with
-    exact scaling by 2^k in the normal range), so the gradients agree exactly."""
-    params, x, phi, det = _setup(seed=3, B=8)
-    o, cache = mlp.forward(params, x, round16=False)
-    _, g = mlp.loss_and_grad_out(o, phi, det, 300.0)
-    a = mlp.backward(params, cache, g, round16=False, dz_scale=1.0)
-    b = mlp.backward(params, cache, g, round16=False, dz_scale=8.0)
-    for u, v in zip(a, b):
-        np.testing.assert_array_equal(u, v)
-    o, cache = mlp.forward(params, x, round16=True)
-    _, g = mlp.loss_and_grad_out(o, phi, det, 300.0)
-    c = mlp.backward(params, cache, g, round16=True, dz_scale=8.0)
-    d = mlp.backward(params, cache, g, round16=True, dz_scale=16.0)
-    for u, v in zip(c, d):
-        np.testing.assert_array_equal(u, v)
-    # ...and the rounded gradient stays within half precision of the exact one.
-    for u, v in zip(c, a):
-        assert np.linalg.norm(u - v) <= 5e-3 * np.linalg.norm(v) + 1e-12
+def _kernel_arithmetic(params, x, phi, det, phi_scale):
+    """The network evaluated the way the GPU kernels evaluate it, written
+    independently of the bound: x, h1, h2 and the weights rounded to half,
+    products summed in FP32, the back-propagated dz rounded to half at the
+    batch-sum scale, bias gradients from the unrounded dz."""
+    f32, f16 = np.float32, np.float16
+
+    def h(a):
+        return np.asarray(a, f32).astype(f16).astype(f32)
+
+    W1, b1, W2, b2, W3, b3 = params
+    W1h, W2h, W3h = h(W1), h(W2), h(W3)
+    b1, b2, b3 = (np.asarray(b, f32) for b in (b1, b2, b3))
+    B = len(x)
+    xh = h(x)
+    z1 = xh @ W1h.T + b1
+    h1 = h(np.maximum(z1, 0))
+    z2 = h1 @ W2h.T + b2
+    h2 = h(np.maximum(z2, 0))
+    o = h2 @ W3h.T + b3
+    d = np.asarray(det, f32)
+    t = np.asarray(phi, f32) / f32(phi_scale)
+    s = o[:, 1]
+    e = np.exp(-np.abs(s))
+    sig = np.where(s >= 0, 1 / (1 + e), e / (1 + e)).astype(f32)
+    g = np.stack([2 * d * (o[:, 0] - t), sig - d], axis=1).astype(f32)     # batch-sum gradient
+    gW3, gb3 = (g.T @ h2) / f32(B), g.sum(axis=0) / f32(B)
+    dz2 = (g @ W3h) * (z2 > 0)
+    gW2, gb2 = (h(dz2).T @ h1) / f32(B), dz2.sum(axis=0) / f32(B)
+    dz1 = (h(dz2) @ W2h) * (z1 > 0)
+    gW1, gb1 = (h(dz1).T @ xh) / f32(B), dz1.sum(axis=0) / f32(B)
+    return o, [gW1, gb1, gW2, gb2, gW3, gb3]
+
+
+def _bound_case(seed, B=96, nin=40, nh1=48, nh2=32):
+    params, x, phi, det = _setup(seed=seed, B=B, nin=nin, h1=nh1, h2=nh2)
+    x = x * np.exp(np.random.default_rng(seed + 100).uniform(-3, 3, x.shape))   # wide range
+    ref_o, cache = mlp.forward(params, x, round16=True)
+    _, g = mlp.loss_and_grad_out(ref_o, phi, det, 300.0)
+    ref_g = mlp.backward(params, cache, g, round16=True)
+    sim_o, sim_g = _kernel_arithmetic(params, x, phi, det, 300.0)
+    return params, x, phi, det, ref_o, ref_g, sim_o, sim_g
+
+
+def test_error_bound_covers_the_kernel_arithmetic():
+    """error_bound's bar holds the half/FP32 evaluation of the network element
+    by element (the largest error is about a third of the bar here), and is
+    tight enough to matter: a few per cent of the typical gradient (W1's bar
+    is wider, from ReLU masks that may flip on these wide-range inputs)."""
+    for seed in range(6):
+        params, x, phi, det, ref_o, ref_g, sim_o, sim_g = _bound_case(seed)
+        e_o, e_g = mlp.error_bound(params, x, phi, det, 300.0)
+        assert np.all(np.abs(sim_o - ref_o) <= e_o)
+        for name, a, b, e in zip("W1 b1 W2 b2 W3 b3".split(), sim_g, ref_g, e_g):
+            assert np.all(np.abs(a - b) <= e), (seed, name, np.max(np.abs(a - b) / e))
+        for i, tight in ((0, 0.25), (2, 0.02), (4, 0.02)):
+            big = np.abs(ref_g[i]) > 0.1 * np.abs(ref_g[i]).max()
+            assert np.median(e_g[i][big] / np.abs(ref_g[i][big])) < tight, (seed, i)
+
+
+def test_error_bound_needs_its_half_rounding_terms():
+    """With the half unit roundoff understated 16-fold the bound no longer
+    holds the kernel arithmetic: the half-rounding terms carry it."""
+    failed = False
+    for seed in range(6):
+        params, x, phi, det, ref_o, ref_g, sim_o, sim_g = _bound_case(seed)
+        e_o, e_g = mlp.error_bound(params, x, phi, det, 300.0, u=2.0 ** -15)
+        failed |= bool(np.any(np.abs(sim_o - ref_o) > e_o))
+        for a, b, e in zip(sim_g, ref_g, e_g):
+            failed |= bool(np.any(np.abs(a - b) > e))
+    assert failed
+
+
+def test_error_bound_is_zero_for_exact_arithmetic():
+    params, x, phi, det = _setup(seed=2, B=5)
+    e_o, e_g = mlp.error_bound(params, x, phi, det, 300.0, u=0.0, ua=0.0, acc=0.0)
+    assert np.all(e_o == 0) and all(np.all(e == 0) for e in e_g)
