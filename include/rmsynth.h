@@ -103,6 +103,12 @@ int rmsynth_plan_info(rmsynth_plan_t plan, double* K, double* lambda0_sq,
  * Q/U in place and need none (*bytes = 0).  The FP16 split keeps one FP32
  * power-of-two scale per LOS (so that every LOS uses the half range without
  * overflow): round_up(4 max(nlos, 1), 256) bytes.
+ *
+ * Workspaces in general (this call, rmsynth_execute_peaks_workspace_size and
+ * rmsynth_search_workspace_size): the size returned covers the whole call.  A
+ * smaller workspace, of at least the size the same query returns for
+ * min(nlos, 128) LOS, is also accepted: the call then processes the LOS in
+ * batches of as many multiples of 128 as it holds, with the same results.
  */
 int rmsynth_workspace_size(rmsynth_plan_t plan, int64_t nlos, int32_t layout,
                            int32_t precision, size_t* bytes);
@@ -146,8 +152,11 @@ int rmsynth_execute(rmsynth_plan_t plan, const float* Q, const float* U, int64_t
  * grid the transform kernels reduce |F|^2 per (LOS, phi tile) while the tile
  * is still in registers and a small kernel merges the tiles, so the outputs are
  * not read back; the results are identical to the two separate calls.
- *   workspace: at least rmsynth_execute_peaks_workspace_size() bytes (the
- *   FP16 split's per-LOS scales, then 8 bytes per LOS and phi tile of 128).
+ *   workspace: rmsynth_execute_peaks_workspace_size() bytes (the FP16
+ *   split's per-LOS scales, then 16 bytes per LOS and phi tile of 128), or
+ *   less down to its value for 128 LOS (LOS batches, see above).
+ * With Fq, Fu and Fabs all NULL the call is rmsynth_search without the
+ * sub-grid outputs (F is never stored; workspace as rmsynth_search's).
  * Errors as rmsynth_execute.
  */
 int rmsynth_execute_peaks(rmsynth_plan_t plan, const float* Q, const float* U, int64_t nlos,
@@ -159,6 +168,116 @@ int rmsynth_execute_peaks(rmsynth_plan_t plan, const float* Q, const float* U, i
  * needs for nlos LOS in the given layout and precision. */
 int rmsynth_execute_peaks_workspace_size(rmsynth_plan_t plan, int64_t nlos, int32_t layout,
                                          int32_t precision, size_t* bytes);
+
+/*
+ * rmsynth_search -- the per-LOS peak of |F| (Section 2.2 after eq. (14)) of
+ * the transform of eqs. (11), (15)-(16) without storing F: what
+ * rmsynth_execute followed by rmsynth_peaks and rmsynth_peak_fit return, for
+ * a cube whose F would not fit or is not wanted (a 2048^2 x 4001 F is 134 GB).
+ *   Q, U, nlos, layout, precision  as rmsynth_execute.
+ *   idx, phi_pk, amp, q_pk, u_pk   as rmsynth_peaks (idx required, the
+ *            others may be NULL); bit-identical to execute + peaks with the
+ *            same precision.
+ *   phi_fit, amp_fit [nlos] device float or NULL: the sub-grid peak, as
+ *            rmsynth_peak_fit (bit-identical to it on the stored F).
+ *   workspace: rmsynth_search_workspace_size() bytes, or less down to its
+ *            value for 128 LOS (LOS batches).  With a split precision on a
+ *            uniform phi grid the transform kernels reduce each (LOS, 64 phi)
+ *            to a 32-byte record while F is in registers (32 bytes per LOS and
+ *            64 phi); other paths hold F of one batch in the workspace.
+ * Errors as rmsynth_execute.
+ */
+int rmsynth_search(rmsynth_plan_t plan, const float* Q, const float* U, int64_t nlos,
+                   int32_t layout, int32_t precision, int32_t* idx, float* phi_pk, float* amp,
+                   float* q_pk, float* u_pk, float* phi_fit, float* amp_fit, void* workspace,
+                   size_t workspace_bytes, void* stream);
+
+/* rmsynth_search_workspace_size -- device workspace rmsynth_search needs for
+ * the whole of nlos LOS in the given layout and precision. */
+int rmsynth_search_workspace_size(rmsynth_plan_t plan, int64_t nlos, int32_t layout,
+                                  int32_t precision, size_t* bytes);
+
+/*
+ * rmsynth_adjoint -- spectra from Faraday-depth components on the plan's
+ * grid: eq. (4) (P(lambda^2) as the integral of F(phi) exp(2i phi lambda^2))
+ * as a sum over the grid, referred to lambda0^2 as eq. (11) refers F:
+ *   P_lj = sum_k C_lk exp(+2i phi_k (lambda_j^2 - lambda0^2)),
+ * i.e. the adjoint of rmsynth_execute without its K w_j factor (a single
+ * component C_k = 1 gives the unit-amplitude spectrum of a Faraday-thin
+ * screen at phi_k, eqs. (1), (3)).  The model spectra of RM-CLEAN components, or of any
+ * model Faraday dispersion function, come from here.
+ *   Cq, Cu   [nlos][nphi] device float: Re and Im of the components.
+ *   Pq, Pu   [nlos][nchan] device float (LOS-major): Re and Im of P.
+ *   precision  RMSYNTH_FP32 or RMSYNTH_SPLIT_BF16 (the phase tiles are
+ *            generated per element unless the channels are uniform in
+ *            lambda^2); RMSYNTH_SPLIT_FP16 only for channels uniform in
+ *            lambda^2 (EUNSUPPORTED otherwise).
+ *   workspace  rmsynth_adjoint_workspace_size() bytes (0 except FP16), or
+ *            less down to its value for 128 LOS (batches).
+ * Every channel gets a value (weights do not enter).  A LOS with a
+ * non-finite component gets non-finite outputs.
+ * Errors as rmsynth_execute.
+ */
+int rmsynth_adjoint(rmsynth_plan_t plan, const float* Cq, const float* Cu, int64_t nlos,
+                    int32_t precision, float* Pq, float* Pu, void* workspace,
+                    size_t workspace_bytes, void* stream);
+
+/* rmsynth_adjoint_workspace_size -- device workspace rmsynth_adjoint needs
+ * for the whole of nlos LOS. */
+int rmsynth_adjoint_workspace_size(rmsynth_plan_t plan, int64_t nlos, int32_t precision,
+                                   size_t* bytes);
+
+/*
+ * rmsynth_rmclean -- RM-CLEAN of each LOS's Faraday spectrum: the
+ * deconvolution by the RMSF R(phi) of eq. (12) that Section 2.2 names (and the
+ * paper leaves unsupported, Section 4), as Hogbom's iteration on a uniform
+ * phi grid:
+ *   r <- F;  C <- 0;  repeat at most max_iter times:
+ *     p = the lowest index maximising |r_k|^2 (FP32);  stop if |r_p| < cutoff;
+ *     c = gain r_p;  C_p += c;  r_k -= c R((k - p) dphi) for every k;
+ *   restored_k = r_k + sum_m C_m G((k - m) dphi),
+ *   G(x) = exp(-4 ln 2 x^2 / fwhm^2) (Gaussian restoring beam of peak 1).
+ * R is evaluated on the doubled grid (k - p) dphi by the plan's phase
+ * generator (FP64 argument reduction, FP32 accumulation); the loop runs in
+ * FP32.
+ *   Fq, Fu   [nlos][nphi] device float: the spectrum (rmsynth_execute).
+ *   gain     in (0, 1];  cutoff >= 0 (same unit as F);  max_iter >= 0.
+ *   fwhm     of the restoring beam in rad m^-2; <= 0 or NaN: the plan's
+ *            fwhm_est (eq. (20)).
+ *   rq, ru   [nlos][nphi] device float: the residual r (may be Fq, Fu:
+ *            in place).
+ *   cq, cu   [nlos][nphi] device float: the components C (zero elsewhere).
+ *   Rq, Ru   [nlos][nphi] device float or both NULL: the restored spectrum.
+ *   niter    [nlos] device int32 or NULL: iterations taken; -1 for a LOS
+ *            whose F is not finite (its outputs are then all NaN).
+ *   workspace  rmsynth_rmclean_workspace_size() bytes (the two tables).
+ * Requires a uniform phi grid and nphi <= 4096 (EUNSUPPORTED otherwise).
+ * Components, restored spectrum and workspace must not overlap other buffers.
+ */
+int rmsynth_rmclean(rmsynth_plan_t plan, const float* Fq, const float* Fu, int64_t nlos,
+                    float gain, float cutoff, int32_t max_iter, double fwhm, float* rq, float* ru,
+                    float* cq, float* cu, float* Rq, float* Ru, int32_t* niter, void* workspace,
+                    size_t workspace_bytes, void* stream);
+
+/* rmsynth_rmclean_workspace_size -- device workspace rmsynth_rmclean needs:
+ * 12 (2 nphi - 1) bytes, rounded up. */
+int rmsynth_rmclean_workspace_size(rmsynth_plan_t plan, size_t* bytes);
+
+/*
+ * rmsynth_peak_fit -- sub-grid Faraday depth and amplitude of each LOS's peak
+ * (an extension: the paper reports phi_peak on the grid, Section 2.2 after
+ * eq. (14)): the vertex of the parabola through |F| at idx - 1, idx, idx + 1
+ * (any grid spacing), |F| being the FP64 square root of the FP32
+ * Fq^2 + Fu^2 the peak search compares; the arithmetic is FP64.
+ *   Fq, Fu   [nlos][nphi] device float; idx [nlos] device int32 (as written
+ *            by rmsynth_peaks).
+ *   phi_fit, amp_fit [nlos] device float (either may be NULL, not both):
+ *            the vertex; the grid values phi[idx], |F|(idx) where a
+ *            neighbour is off the grid or the parabola does not open
+ *            downwards; NaN where idx = -1.
+ */
+int rmsynth_peak_fit(rmsynth_plan_t plan, const float* Fq, const float* Fu, const int32_t* idx,
+                     int64_t nlos, float* phi_fit, float* amp_fit, void* stream);
 
 /*
  * rmsynth_peaks -- per-LOS peak of |F| (the Faraday depth phi_peak where |F|

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cfloat>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -42,6 +43,7 @@ namespace {
 void free_plan(rmsynth_plan_s* p)
 {
     if (!p) return;
+    free_plan(p->adj);
     void* bufs[] = {p->d_b, p->d_lambda2, p->d_w, p->d_phi, p->d_base, p->d_Tbf[0], p->d_Tbf[1],
                     p->d_Thf[0], p->d_Thf[1]};
     for (void* b : bufs)
@@ -84,6 +86,48 @@ int build_factor_tables(rmsynth_plan_s* p)
     (void)hipStreamDestroy(s);
     if (e != hipSuccess) return rms_hip_fail(e, "rmsynth_plan: phase-table kernel");
     if (e2 != hipSuccess) return rms_hip_fail(e2, "rmsynth_plan: phase-table kernel");
+    return RMSYNTH_OK;
+}
+
+// The plan of the adjoint transform (spectra from Faraday-depth components,
+// eq. (4) as a sum over the grid, referred to lambda0^2):
+//   P_lj = sum_k C_lk exp(+2i phi_k a_j),   a_j = lambda_j^2 - lambda0^2.
+// It is the forward contraction with the roles of the two axes exchanged:
+// the phi_k become the contracted "channels" (b = phi_k / pi, weight 1,
+// K = 1) and -a_j the output grid, so exp(-2i (-a_j) phi_k) is the wanted
+// exp(+2i phi_k a_j); the forward kernels run it unchanged.
+int build_adjoint_plan(rmsynth_plan_s* p, const double* lambda2, const double* phi)
+{
+    auto* q = new (std::nothrow) rmsynth_plan_s{};
+    if (!q) return rms_fail(RMSYNTH_ENOMEM, "rmsynth_plan: host allocation");
+    p->adj = q;
+    q->device = p->device;
+    q->nchan = p->nphi;
+    q->nphi = p->nchan;
+    q->nchan_pad = (int32_t)round_up(q->nchan, kChanPad);
+    q->nphi_pad = (int32_t)round_up(q->nphi, kPhiPad);
+    q->K = 1.0;
+    q->lambda0_sq = 0.0;
+    std::vector<double> hb(q->nchan_pad, 0.0), hgrid(q->nphi_pad, 0.0);
+    std::vector<float> hw(q->nchan_pad, 0.0f);
+    double amax = 0.0;
+    for (int32_t k = 0; k < p->nphi; ++k) {
+        hb[k] = phi[k] / M_PI;
+        hw[k] = 1.0f;
+        amax = std::max(amax, std::fabs(phi[k]));
+    }
+    for (int32_t j = 0; j < p->nchan; ++j) hgrid[j] = -(lambda2[j] - p->lambda0_sq);
+    hipError_t e;
+    if ((e = hipMalloc(&q->d_b, sizeof(double) * q->nchan_pad)) != hipSuccess ||
+        (e = hipMalloc(&q->d_w, sizeof(float) * q->nchan_pad)) != hipSuccess ||
+        (e = hipMalloc(&q->d_phi, sizeof(double) * q->nphi_pad)) != hipSuccess)
+        return rms_fail(RMSYNTH_ENOMEM, "rmsynth_plan: hipMalloc (adjoint): %s", hipGetErrorString(e));
+    if ((e = hipMemcpy(q->d_b, hb.data(), sizeof(double) * q->nchan_pad, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(q->d_w, hw.data(), sizeof(float) * q->nchan_pad, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(q->d_phi, hgrid.data(), sizeof(double) * q->nphi_pad, hipMemcpyHostToDevice)) != hipSuccess)
+        return rms_hip_fail(e, "rmsynth_plan: hipMemcpy (adjoint)");
+    q->uniform = detect_uniform(hgrid.data(), q->nphi, amax, &q->phi0, &q->dphi);
+    if (q->uniform) return build_factor_tables(q);
     return RMSYNTH_OK;
 }
 
@@ -183,6 +227,10 @@ int rmsynth_plan(const double* lambda2, const double* weights, int32_t nchan, co
             return rc;
         }
     }
+    if (int rc = build_adjoint_plan(p, lambda2, phi)) {
+        free_plan(p);
+        return rc;
+    }
     *out = p;
     return rms_ok();
 }
@@ -226,7 +274,9 @@ int rmsynth_rmsf(rmsynth_plan_t p, float* R_re, float* R_im, void* stream)
 
 namespace {
 
-size_t scale_bytes(int64_t nlos) { return (size_t)round_up(std::max<int64_t>(nlos, 1) * 4, 256); }
+size_t region(int64_t n, int64_t bytes_each) { return (size_t)round_up(std::max<int64_t>(n, 1) * bytes_each, 256); }
+
+size_t scale_bytes(int64_t nlos) { return region(nlos, 4); }
 
 bool fused_peaks(const rmsynth_plan_s* p, int32_t precision)
 {
@@ -247,37 +297,96 @@ int check_execute_args(const rmsynth_plan_s* p, int64_t nlos, int32_t layout, in
     return RMSYNTH_OK;
 }
 
-// The transform in LOS batches (each grid within the dispatch limit, tiles of
-// at least 64 LOS of 256 threads); with parts, the factored kernels also
-// write their per-tile peaks.
-int run_execute(const rmsynth_plan_s* p, const float* Q, const float* U, int64_t nlos, int32_t layout,
-                int32_t precision, float* Fq, float* Fu, float* Fabs, float* scales, PeakPart* parts,
-                hipStream_t stream, const char* who)
+// What a call keeps in its workspace for a batch of n LOS.
+enum class Mode { Execute, ExecutePeaks, Search };
+
+struct WsLayout {
+    size_t scales = 0;  // FP16 split: per-LOS scales
+    size_t parts = 0;   // fused peaks with F stored: PeakPart records
+    size_t recs = 0;    // fused search: PeakRec records
+    size_t fq = 0, fu = 0;  // search on the unfused paths: F of the batch
+    size_t total() const { return scales + parts + recs + fq + fu; }
+};
+
+WsLayout ws_layout(const rmsynth_plan_s* p, Mode mode, int32_t precision, int64_t n)
+{
+    WsLayout w;
+    if (precision == RMSYNTH_SPLIT_FP16) w.scales = scale_bytes(n);
+    if (mode == Mode::ExecutePeaks && fused_peaks(p, precision))
+        w.parts = region(n, factored_peak_parts(*p) * (int64_t)sizeof(PeakPart));
+    if (mode == Mode::Search) {
+        if (fused_peaks(p, precision)) {
+            w.recs = region(n, factored_peak_parts(*p) * (int64_t)sizeof(PeakRec));
+        } else {
+            w.fq = region(n, (int64_t)p->nphi * 4);
+            w.fu = w.fq;
+        }
+    }
+    return w;
+}
+
+// LOS per batch for a workspace of `bytes`: all of them when it holds the
+// whole call's needs, else the largest multiple of kBatchLos it holds.
+constexpr int64_t kBatchLos = 128;
+
+int batch_size(const rmsynth_plan_s* p, Mode mode, int32_t precision, int64_t nlos, size_t bytes,
+               bool have_ws, int64_t* batch, const char* who)
+{
+    const size_t whole = ws_layout(p, mode, precision, nlos).total();
+    if (whole == 0 || (have_ws && bytes >= whole)) {
+        *batch = nlos;
+        return RMSYNTH_OK;
+    }
+    const int64_t first = std::min(nlos, kBatchLos);
+    const size_t least = ws_layout(p, mode, precision, first).total();
+    if (!have_ws || bytes < least)
+        return rms_fail(RMSYNTH_EWORKSPACE, "%s: needs %zu workspace bytes (%zu for the whole call), got %zu",
+                        who, least, whole, have_ws ? bytes : (size_t)0);
+    // The layout grows linearly in n (plus at most 255 bytes of rounding per region).
+    int64_t lo = first, hi = nlos;
+    while (hi - lo > kBatchLos) {
+        const int64_t mid = lo + (hi - lo) / 2 / kBatchLos * kBatchLos;
+        if (ws_layout(p, mode, precision, mid).total() <= bytes) lo = mid;
+        else hi = mid;
+    }
+    *batch = lo;
+    return RMSYNTH_OK;
+}
+
+// The transform of one batch of n LOS starting at LOS l0 of the call, in
+// launches whose grids stay within the dispatch limit (tiles of at least 64
+// LOS of 256 threads).  ld is the call's row stride (LOS-major: nchan) or
+// plane stride (frequency-major: the call's nlos).  With parts or recs the
+// factored kernels also write their per-tile peaks, laid out [part][n].
+int run_execute(const rmsynth_plan_s* p, const float* Q, const float* U, int64_t l0, int64_t n,
+                int64_t ld, int32_t layout, int32_t precision, float* Fq, float* Fu, float* Fabs,
+                float* scales, PeakPart* parts, PeakRec* recs, hipStream_t stream, const char* who)
 {
     const int64_t tiles_n = (p->nphi + 127) / 128;
     const int64_t max_los = max_los_tiled(tiles_n, 64, 256);
-    for (int64_t l0 = 0; l0 < nlos;) {
-        const int64_t n = std::min(nlos - l0, max_los);
+    for (int64_t b0 = 0; b0 < n;) {
+        const int64_t m = std::min(n - b0, max_los);
+        const int64_t l = l0 + b0;
         ExecArgs a{};
         if (layout == RMSYNTH_LOS_MAJOR) {
-            a.Q = Q + l0 * p->nchan;
-            a.U = U + l0 * p->nchan;
-            a.ld = p->nchan;
-            a.vec4 = (p->nchan % 4 == 0) && ((uintptr_t)Q % 16 == 0) && ((uintptr_t)U % 16 == 0);
+            a.Q = Q + l * ld;
+            a.U = U + l * ld;
+            a.vec4 = (ld % 4 == 0) && ((uintptr_t)Q % 16 == 0) && ((uintptr_t)U % 16 == 0);
         } else {
-            a.Q = Q + l0;
-            a.U = U + l0;
-            a.ld = nlos;
+            a.Q = Q + l;
+            a.U = U + l;
             a.vec4 = false;
         }
-        a.nlos = n;
+        a.ld = ld;
+        a.nlos = m;
         a.layout = layout;
-        a.Fq = Fq + l0 * p->nphi;
-        a.Fu = Fu + l0 * p->nphi;
-        a.Fabs = Fabs ? Fabs + l0 * p->nphi : nullptr;
-        a.los_scale = precision == RMSYNTH_SPLIT_FP16 ? scales + l0 : nullptr;
-        a.peak_part = parts ? parts + l0 : nullptr;
-        a.peak_part_ld = nlos;
+        a.Fq = Fq ? Fq + b0 * p->nphi : nullptr;
+        a.Fu = Fu ? Fu + b0 * p->nphi : nullptr;
+        a.Fabs = Fabs ? Fabs + b0 * p->nphi : nullptr;
+        a.los_scale = precision == RMSYNTH_SPLIT_FP16 ? scales + b0 : nullptr;
+        a.peak_part = parts ? parts + b0 : nullptr;
+        a.peak_rec = recs ? recs + b0 : nullptr;
+        a.peak_part_ld = n;
         a.stream = stream;
         if (precision == RMSYNTH_SPLIT_FP16) {
             hipError_t e = launch_los_scale(*p, a);
@@ -288,12 +397,74 @@ int run_execute(const rmsynth_plan_s* p, const float* Q, const float* U, int64_t
         else if (p->uniform) e = launch_synth_factored(*p, a, precision);
         else e = launch_synth_split(*p, a, precision);
         if (e != hipSuccess) return rms_hip_fail(e, who);
-        l0 += n;
+        b0 += m;
+    }
+    return RMSYNTH_OK;
+}
+
+struct PeakOut {
+    int32_t* idx;
+    float *phi_pk, *amp, *q_pk, *u_pk, *phi_fit, *amp_fit;
+    PeakOut at(int64_t l) const
+    {
+        auto o = [l](float* x) { return x ? x + l : nullptr; };
+        return PeakOut{idx + l, o(phi_pk), o(amp), o(q_pk), o(u_pk), o(phi_fit), o(amp_fit)};
+    }
+};
+
+// One call of execute / execute_peaks / search over all nlos, in batches that
+// fit the workspace.
+int run_batched(const rmsynth_plan_s* p, Mode mode, const float* Q, const float* U, int64_t nlos,
+                int32_t layout, int32_t precision, float* Fq, float* Fu, float* Fabs,
+                const PeakOut& out, void* workspace, size_t workspace_bytes, hipStream_t s,
+                const char* who)
+{
+    int64_t batch = 0;
+    if (int rc = batch_size(p, mode, precision, nlos, workspace_bytes, workspace != nullptr, &batch, who))
+        return rc;
+    const int64_t ld = layout == RMSYNTH_LOS_MAJOR ? p->nchan : nlos;
+    const bool fused = fused_peaks(p, precision);
+    for (int64_t l0 = 0; l0 < nlos; l0 += batch) {
+        const int64_t n = std::min(batch, nlos - l0);
+        const WsLayout w = ws_layout(p, mode, precision, n);
+        char* ws = static_cast<char*>(workspace);
+        float* scales = w.scales ? reinterpret_cast<float*>(ws) : nullptr;
+        ws += w.scales;
+        PeakPart* parts = w.parts ? reinterpret_cast<PeakPart*>(ws) : nullptr;
+        ws += w.parts;
+        PeakRec* recs = w.recs ? reinterpret_cast<PeakRec*>(ws) : nullptr;
+        ws += w.recs;
+        float* bq = Fq ? Fq + l0 * p->nphi : (w.fq ? reinterpret_cast<float*>(ws) : nullptr);
+        ws += w.fq;
+        float* bu = Fu ? Fu + l0 * p->nphi : (w.fu ? reinterpret_cast<float*>(ws) : nullptr);
+        float* ba = Fabs ? Fabs + l0 * p->nphi : nullptr;
+        if (int rc = run_execute(p, Q, U, l0, n, ld, layout, precision, mode == Mode::Search && fused ? nullptr : bq,
+                                 mode == Mode::Search && fused ? nullptr : bu, ba, scales, parts, recs, s, who))
+            return rc;
+        if (mode == Mode::Execute) continue;
+        const PeakOut o = out.at(l0);
+        hipError_t e = hipSuccess;
+        if (recs)
+            e = launch_peak_merge_rec(*p, recs, n, n, o.idx, o.phi_pk, o.amp, o.q_pk, o.u_pk, o.phi_fit,
+                                      o.amp_fit, s);
+        else if (parts)
+            e = launch_peak_merge(*p, parts, n, bq, bu, o.idx, o.phi_pk, o.amp, o.q_pk, o.u_pk, s);
+        else {
+            e = launch_peaks(*p, bq, bu, n, o.idx, o.phi_pk, o.amp, o.q_pk, o.u_pk, s);
+            if (e == hipSuccess && (o.phi_fit || o.amp_fit))
+                e = launch_peak_fit(*p, bq, bu, o.idx, n, o.phi_fit, o.amp_fit, s);
+        }
+        if (e != hipSuccess) return rms_hip_fail(e, who);
     }
     return RMSYNTH_OK;
 }
 
 }  // namespace
+
+size_t search_workspace_bytes(const rmsynth_plan_s* p, int64_t n, int32_t precision)
+{
+    return ws_layout(p, Mode::Search, precision, n).total();
+}
 
 extern "C" {
 
@@ -301,19 +472,13 @@ int rmsynth_execute(rmsynth_plan_t p, const float* Q, const float* U, int64_t nl
                     int32_t precision, float* Fq, float* Fu, float* Fabs, void* workspace,
                     size_t workspace_bytes, void* stream)
 {
-    if (int rc = check_execute_args(p, nlos, layout, precision, "rmsynth_execute")) return rc;
+    const char* who = "rmsynth_execute";
+    if (int rc = check_execute_args(p, nlos, layout, precision, who)) return rc;
     if (nlos == 0) return rms_ok();
-    if (!Q || !U || !Fq || !Fu) return rms_fail(RMSYNTH_EINVAL, "rmsynth_execute: NULL buffer");
-    if (precision == RMSYNTH_SPLIT_FP16) {
-        const size_t need = (size_t)round_up(nlos * 4, 256);
-        if (!workspace || workspace_bytes < need)
-            return rms_fail(RMSYNTH_EWORKSPACE, "rmsynth_execute: FP16 split needs %zu workspace bytes, got %zu",
-                            need, workspace ? workspace_bytes : (size_t)0);
-    }
+    if (!Q || !U || !Fq || !Fu) return rms_fail(RMSYNTH_EINVAL, "%s: NULL buffer", who);
     if (int rc = check_device(p)) return rc;
-    if (int rc = run_execute(p, Q, U, nlos, layout, precision, Fq, Fu, Fabs,
-                             static_cast<float*>(workspace), nullptr, (hipStream_t)stream,
-                             "rmsynth_execute launch"))
+    if (int rc = run_batched(p, Mode::Execute, Q, U, nlos, layout, precision, Fq, Fu, Fabs, PeakOut{},
+                             workspace, workspace_bytes, (hipStream_t)stream, who))
         return rc;
     return rms_ok();
 }
@@ -324,12 +489,48 @@ int rmsynth_execute_peaks_workspace_size(rmsynth_plan_t p, int64_t nlos, int32_t
     if (!bytes) return rms_fail(RMSYNTH_EINVAL, "rmsynth_execute_peaks_workspace_size: bytes is NULL");
     if (int rc = check_execute_args(p, nlos, layout, precision, "rmsynth_execute_peaks_workspace_size"))
         return rc;
-    size_t b = precision == RMSYNTH_SPLIT_FP16 ? scale_bytes(nlos) : 0;
-    if (fused_peaks(p, precision))
-        b += (size_t)round_up(std::max<int64_t>(nlos, 1) * factored_peak_parts(*p) * (int64_t)sizeof(PeakPart), 256);
-    *bytes = b;
+    *bytes = ws_layout(p, Mode::ExecutePeaks, precision, nlos).total();
     return rms_ok();
 }
+
+int rmsynth_search_workspace_size(rmsynth_plan_t p, int64_t nlos, int32_t layout, int32_t precision,
+                                  size_t* bytes)
+{
+    if (!bytes) return rms_fail(RMSYNTH_EINVAL, "rmsynth_search_workspace_size: bytes is NULL");
+    if (int rc = check_execute_args(p, nlos, layout, precision, "rmsynth_search_workspace_size"))
+        return rc;
+    *bytes = ws_layout(p, Mode::Search, precision, nlos).total();
+    return rms_ok();
+}
+
+int rmsynth_search(rmsynth_plan_t p, const float* Q, const float* U, int64_t nlos, int32_t layout,
+                   int32_t precision, int32_t* idx, float* phi_pk, float* amp, float* q_pk,
+                   float* u_pk, float* phi_fit, float* amp_fit, void* workspace,
+                   size_t workspace_bytes, void* stream)
+{
+    return search_impl(p, Q, U, nlos, layout, precision, idx, phi_pk, amp, q_pk, u_pk, phi_fit,
+                       amp_fit, workspace, workspace_bytes, stream, "rmsynth_search");
+}
+
+}  // extern "C"
+
+int search_impl(const rmsynth_plan_s* p, const float* Q, const float* U, int64_t nlos,
+                int32_t layout, int32_t precision, int32_t* idx, float* phi_pk, float* amp,
+                float* q_pk, float* u_pk, float* phi_fit, float* amp_fit, void* workspace,
+                size_t workspace_bytes, void* stream, const char* who)
+{
+    if (int rc = check_execute_args(p, nlos, layout, precision, who)) return rc;
+    if (nlos == 0) return rms_ok();
+    if (!Q || !U || !idx) return rms_fail(RMSYNTH_EINVAL, "%s: NULL buffer", who);
+    if (int rc = check_device(p)) return rc;
+    const PeakOut out{idx, phi_pk, amp, q_pk, u_pk, phi_fit, amp_fit};
+    if (int rc = run_batched(p, Mode::Search, Q, U, nlos, layout, precision, nullptr, nullptr, nullptr, out,
+                             workspace, workspace_bytes, (hipStream_t)stream, who))
+        return rc;
+    return rms_ok();
+}
+
+extern "C" {
 
 int rmsynth_execute_peaks(rmsynth_plan_t p, const float* Q, const float* U, int64_t nlos,
                           int32_t layout, int32_t precision, float* Fq, float* Fu, float* Fabs,
@@ -339,29 +540,94 @@ int rmsynth_execute_peaks(rmsynth_plan_t p, const float* Q, const float* U, int6
     const char* who = "rmsynth_execute_peaks";
     if (int rc = check_execute_args(p, nlos, layout, precision, who)) return rc;
     if (nlos == 0) return rms_ok();
+    if (!Fq && !Fu && !Fabs)  // peaks only: F is never stored
+        return rmsynth_search(p, Q, U, nlos, layout, precision, idx, phi_pk, amp, q_pk, u_pk, nullptr,
+                              nullptr, workspace, workspace_bytes, stream);
     if (!Q || !U || !Fq || !Fu || !idx) return rms_fail(RMSYNTH_EINVAL, "%s: NULL buffer", who);
-    size_t need = 0;
-    if (int rc = rmsynth_execute_peaks_workspace_size(p, nlos, layout, precision, &need)) return rc;
-    if (need && (!workspace || workspace_bytes < need))
+    if (int rc = check_device(p)) return rc;
+    const PeakOut out{idx, phi_pk, amp, q_pk, u_pk, nullptr, nullptr};
+    if (int rc = run_batched(p, Mode::ExecutePeaks, Q, U, nlos, layout, precision, Fq, Fu, Fabs, out,
+                             workspace, workspace_bytes, (hipStream_t)stream, who))
+        return rc;
+    return rms_ok();
+}
+
+int rmsynth_adjoint_workspace_size(rmsynth_plan_t p, int64_t nlos, int32_t precision, size_t* bytes)
+{
+    if (!bytes) return rms_fail(RMSYNTH_EINVAL, "rmsynth_adjoint_workspace_size: bytes is NULL");
+    if (!p) return rms_fail(RMSYNTH_EINVAL, "rmsynth_adjoint_workspace_size: plan is NULL");
+    if (int rc = check_execute_args(p->adj, nlos, RMSYNTH_LOS_MAJOR, precision,
+                                    "rmsynth_adjoint_workspace_size"))
+        return rc;
+    *bytes = ws_layout(p->adj, Mode::Execute, precision, nlos).total();
+    return rms_ok();
+}
+
+int rmsynth_adjoint(rmsynth_plan_t p, const float* Cq, const float* Cu, int64_t nlos, int32_t precision,
+                    float* Pq, float* Pu, void* workspace, size_t workspace_bytes, void* stream)
+{
+    const char* who = "rmsynth_adjoint";
+    if (!p) return rms_fail(RMSYNTH_EINVAL, "%s: plan is NULL", who);
+    if (precision == RMSYNTH_SPLIT_FP16 && !p->adj->uniform)
+        return rms_fail(RMSYNTH_EUNSUPPORTED, "%s: the FP16 split needs channels uniform in lambda^2", who);
+    if (int rc = check_execute_args(p->adj, nlos, RMSYNTH_LOS_MAJOR, precision, who)) return rc;
+    if (nlos == 0) return rms_ok();
+    if (!Cq || !Cu || !Pq || !Pu) return rms_fail(RMSYNTH_EINVAL, "%s: NULL buffer", who);
+    if (int rc = check_device(p)) return rc;
+    if (int rc = run_batched(p->adj, Mode::Execute, Cq, Cu, nlos, RMSYNTH_LOS_MAJOR, precision, Pq, Pu,
+                             nullptr, PeakOut{}, workspace, workspace_bytes, (hipStream_t)stream, who))
+        return rc;
+    return rms_ok();
+}
+
+int rmsynth_rmclean_workspace_size(rmsynth_plan_t p, size_t* bytes)
+{
+    if (!p || !bytes) return rms_fail(RMSYNTH_EINVAL, "rmsynth_rmclean_workspace_size: NULL argument");
+    *bytes = rmclean_table_bytes(*p);
+    return rms_ok();
+}
+
+int rmsynth_rmclean(rmsynth_plan_t p, const float* Fq, const float* Fu, int64_t nlos, float gain,
+                    float cutoff, int32_t max_iter, double fwhm, float* rq, float* ru, float* cq,
+                    float* cu, float* Rq, float* Ru, int32_t* niter, void* workspace,
+                    size_t workspace_bytes, void* stream)
+{
+    const char* who = "rmsynth_rmclean";
+    if (!p) return rms_fail(RMSYNTH_EINVAL, "%s: plan is NULL", who);
+    if (nlos < 0) return rms_fail(RMSYNTH_EINVAL, "%s: nlos=%lld", who, (long long)nlos);
+    if (!p->uniform) return rms_fail(RMSYNTH_EUNSUPPORTED, "%s: needs a uniform phi grid", who);
+    if (p->nphi > kRmcleanMaxPhi)
+        return rms_fail(RMSYNTH_EUNSUPPORTED, "%s: nphi=%d above %d", who, p->nphi, kRmcleanMaxPhi);
+    if (!(gain > 0.0f && gain <= 1.0f)) return rms_fail(RMSYNTH_EINVAL, "%s: gain=%g", who, (double)gain);
+    if (!(cutoff >= 0.0f && cutoff <= FLT_MAX)) return rms_fail(RMSYNTH_EINVAL, "%s: cutoff=%g", who, (double)cutoff);
+    if (max_iter < 0) return rms_fail(RMSYNTH_EINVAL, "%s: max_iter=%d", who, max_iter);
+    if (std::isnan(fwhm) || fwhm <= 0.0) fwhm = p->fwhm_est;
+    if (!(fwhm > 0.0 && std::isfinite(fwhm))) return rms_fail(RMSYNTH_EINVAL, "%s: fwhm=%g", who, fwhm);
+    if (nlos == 0) return rms_ok();
+    if (!Fq || !Fu || !rq || !ru || !cq || !cu || (!Rq) != (!Ru))
+        return rms_fail(RMSYNTH_EINVAL, "%s: NULL buffer", who);
+    const size_t need = rmclean_table_bytes(*p);
+    if (!workspace || workspace_bytes < need)
         return rms_fail(RMSYNTH_EWORKSPACE, "%s: needs %zu workspace bytes, got %zu", who, need,
                         workspace ? workspace_bytes : (size_t)0);
     if (int rc = check_device(p)) return rc;
-    hipStream_t s = (hipStream_t)stream;
-    char* ws = static_cast<char*>(workspace);
-    float* scales = reinterpret_cast<float*>(ws);
-    const size_t sb = precision == RMSYNTH_SPLIT_FP16 ? scale_bytes(nlos) : 0;
-    if (!fused_peaks(p, precision)) {
-        if (int rc = run_execute(p, Q, U, nlos, layout, precision, Fq, Fu, Fabs, scales, nullptr, s, who))
-            return rc;
-        hipError_t e = launch_peaks(*p, Fq, Fu, nlos, idx, phi_pk, amp, q_pk, u_pk, s);
-        if (e != hipSuccess) return rms_hip_fail(e, who);
-        return rms_ok();
-    }
-    PeakPart* parts = reinterpret_cast<PeakPart*>(ws + sb);
-    if (int rc = run_execute(p, Q, U, nlos, layout, precision, Fq, Fu, Fabs, scales, parts, s, who))
-        return rc;
-    hipError_t e = launch_peak_merge(*p, parts, nlos, Fq, Fu, idx, phi_pk, amp, q_pk, u_pk, s);
-    if (e != hipSuccess) return rms_hip_fail(e, who);
+    hipError_t e = launch_rmclean(*p, Fq, Fu, nlos, gain, cutoff, max_iter, fwhm, rq, ru, cq, cu, Rq, Ru,
+                                  niter, workspace, (hipStream_t)stream);
+    if (e != hipSuccess) return rms_hip_fail(e, "rmsynth_rmclean launch");
+    return rms_ok();
+}
+
+int rmsynth_peak_fit(rmsynth_plan_t p, const float* Fq, const float* Fu, const int32_t* idx,
+                     int64_t nlos, float* phi_fit, float* amp_fit, void* stream)
+{
+    if (!p) return rms_fail(RMSYNTH_EINVAL, "rmsynth_peak_fit: plan is NULL");
+    if (nlos < 0) return rms_fail(RMSYNTH_EINVAL, "rmsynth_peak_fit: nlos=%lld", (long long)nlos);
+    if (nlos == 0) return rms_ok();
+    if (!Fq || !Fu || !idx || (!phi_fit && !amp_fit))
+        return rms_fail(RMSYNTH_EINVAL, "rmsynth_peak_fit: NULL buffer");
+    if (int rc = check_device(p)) return rc;
+    hipError_t e = launch_peak_fit(*p, Fq, Fu, idx, nlos, phi_fit, amp_fit, (hipStream_t)stream);
+    if (e != hipSuccess) return rms_hip_fail(e, "rmsynth_peak_fit launch");
     return rms_ok();
 }
 

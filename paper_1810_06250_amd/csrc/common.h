@@ -44,6 +44,9 @@ struct rmsynth_plan_s {
     uint4* d_Tbf[2];
     uint4* d_Thf[2];
     bool any_flagged;    // some channel has weight 0
+    // The adjoint transform's plan (axes exchanged, see build_adjoint_plan);
+    // owned, NULL inside an adjoint plan itself.
+    rmsynth_plan_s* adj;
 };
 
 constexpr int kFactorTile = 128;  // phi per tile of the factored kernels
@@ -123,6 +126,26 @@ __device__ __forceinline__ uint32_t swap_negate(uint32_t d)
     return __builtin_amdgcn_alignbit(d, d, 16) ^ 0x80000000u;
 }
 
+// Sub-grid peak (an extension; the paper reports the grid peak): the vertex
+// of the parabola through (x0, y0), (x1, y1), (x2, y2), x0 < x1 < x2, y1 the
+// grid maximum, in FP64.  A missing neighbour (NaN: the peak is at an end of
+// the grid) or a parabola that does not open downwards leaves the grid values.
+__device__ __forceinline__ void parabola_vertex(double x0, double y0, double x1, double y1,
+                                                double x2, double y2, float* phi_fit,
+                                                float* amp_fit)
+{
+    const double d0 = x0 - x1, d2 = x2 - x1;
+    const double s0 = (y0 - y1) / d0, s2 = (y2 - y1) / d2;
+    const double A = (s0 - s2) / (d0 - d2);
+    const double B = s0 - A * d0;
+    const double t = -B / (2.0 * A);
+    const double top = y1 - B * B / (4.0 * A);
+    const bool ok = __builtin_isfinite(y0) && __builtin_isfinite(y2) && __builtin_isfinite(t) &&
+                    A < 0.0;
+    *phi_fit = (float)(ok ? x1 + t : x1);
+    *amp_fit = (float)(ok ? top : y1);
+}
+
 // Map a hardware workgroup id to a logical tile so that logical neighbours
 // (the phi tiles of one LOS tile, which read the same Q/U rows) run on the
 // same XCD: workgroups are dispatched round-robin over the 8 XCDs, each with
@@ -143,6 +166,20 @@ struct PeakPart {
     int32_t idx;
 };
 
+// The same for a transform that stores no F: the record also carries Fq, Fu
+// at the peak and the |F|^2 around it that the sub-grid fit needs: at the
+// neighbours inside the 64 phi (prv, nxt) and at both ends of the 64 (first,
+// last), so that a neighbour across the boundary is found in the adjacent
+// record.  -1 marks a value that is not there (before the first phi of the
+// 64, or past the end of the grid).
+struct PeakRec {
+    float m;
+    int32_t idx;
+    float q, u;
+    float prv, nxt;
+    float first, last;
+};
+
 struct ExecArgs {
     const float* Q;
     const float* U;
@@ -156,6 +193,8 @@ struct ExecArgs {
     float* los_scale;  // FP16 split: per-LOS scale [nlos] in the workspace
     PeakPart* peak_part;  // factored kernels: per-(LOS, half phi tile) peaks, or NULL;
     int64_t peak_part_ld; // record (h, l) at peak_part[h * peak_part_ld + l]
+    PeakRec* peak_rec;    // factored kernels, F not stored (Fq = Fu = NULL): full
+                          // records at peak_rec[h * peak_part_ld + l], or NULL
     hipStream_t stream;
 };
 
@@ -176,6 +215,33 @@ int factored_peak_parts(const rmsynth_plan_s& p);
 hipError_t launch_peak_merge(const rmsynth_plan_s& p, const PeakPart* part, int64_t nlos,
                              const float* Fq, const float* Fu, int32_t* idx, float* phi_pk,
                              float* amp, float* q_pk, float* u_pk, hipStream_t s);
+// Merge of full records (no F stored), with the sub-grid fit; records at
+// rec[h * rec_ld + l] for the nlos LOS of a batch.
+hipError_t launch_peak_merge_rec(const rmsynth_plan_s& p, const PeakRec* rec, int64_t rec_ld,
+                                 int64_t nlos, int32_t* idx, float* phi_pk, float* amp,
+                                 float* q_pk, float* u_pk, float* phi_fit, float* amp_fit,
+                                 hipStream_t s);
+// RM-CLEAN (rmclean.hip): workspace bytes for the doubled-grid RMSF and beam
+// tables, and the launch (tables, then one wave per LOS).
+constexpr int kRmcleanMaxPhi = 4096;  // residual of a LOS held in one wave's registers
+size_t rmclean_table_bytes(const rmsynth_plan_s& p);
+hipError_t launch_rmclean(const rmsynth_plan_s& p, const float* Fq, const float* Fu, int64_t nlos,
+                          float gain, float cutoff, int max_iter, double fwhm, float* rq, float* ru,
+                          float* cq, float* cu, float* Rq, float* Ru, int32_t* niter, void* ws,
+                          hipStream_t s);
+// Sub-grid fit from stored F around given peak indices (peaks.hip).
+hipError_t launch_peak_fit(const rmsynth_plan_s& p, const float* Fq, const float* Fu,
+                           const int32_t* idx, int64_t nlos, float* phi_fit, float* amp_fit,
+                           hipStream_t s);
+
+// The peaks-only search of rmsynth_search on a given workspace (any size down
+// to one 128-LOS batch); `who` names the entry point in error messages.
+int search_impl(const rmsynth_plan_s* p, const float* Q, const float* U, int64_t nlos,
+                int32_t layout, int32_t precision, int32_t* idx, float* phi_pk, float* amp,
+                float* q_pk, float* u_pk, float* phi_fit, float* amp_fit, void* workspace,
+                size_t workspace_bytes, void* stream, const char* who);
+// Workspace bytes rmsynth_search needs for n LOS (0 < n).
+size_t search_workspace_bytes(const rmsynth_plan_s* p, int64_t n, int32_t precision);
 
 inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 

@@ -119,7 +119,53 @@ __global__ void peak_angle_kernel(const float* __restrict__ phi_pk, const float*
     chi0[l] = c < (float)pi ? c : 0.0f;
 }
 
+// Sub-grid peak from stored F: |F| at idx - 1, idx, idx + 1 as the square
+// root (FP64) of the FP32 |F|^2 the peak search compares (the same fma), then
+// the parabola's vertex.  idx = -1 gives NaN.
+__global__ void peak_fit_kernel(const float* __restrict__ Fq, const float* __restrict__ Fu,
+                                const int32_t* __restrict__ idx, int64_t nlos, int nphi,
+                                const double* __restrict__ phik, float* __restrict__ phi_fit,
+                                float* __restrict__ amp_fit)
+{
+    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= nlos) return;
+    const int k = idx[l];
+    if (k < 0 || k >= nphi) {
+        if (phi_fit) phi_fit[l] = __builtin_nanf("");
+        if (amp_fit) amp_fit[l] = __builtin_nanf("");
+        return;
+    }
+    const float* q = Fq + l * nphi;
+    const float* u = Fu + l * nphi;
+    auto amp_at = [&](int kk) -> double {
+        if (kk < 0 || kk >= nphi) return __builtin_nan("");
+        return __builtin_sqrt((double)__builtin_fmaf(q[kk], q[kk], u[kk] * u[kk]));
+    };
+    const double x0 = k > 0 ? phik[k - 1] : __builtin_nan("");
+    const double x2 = k + 1 < nphi ? phik[k + 1] : __builtin_nan("");
+    float pf, af;
+    parabola_vertex(x0, amp_at(k - 1), phik[k], amp_at(k), x2, amp_at(k + 1), &pf, &af);
+    if (phi_fit) phi_fit[l] = pf;
+    if (amp_fit) amp_fit[l] = af;
+}
+
 }  // namespace
+
+hipError_t launch_peak_fit(const rmsynth_plan_s& p, const float* Fq, const float* Fu,
+                           const int32_t* idx, int64_t nlos, float* phi_fit, float* amp_fit,
+                           hipStream_t s)
+{
+    for (int64_t l0 = 0; l0 < nlos;) {
+        const int64_t n = std::min<int64_t>(nlos - l0, max_items(256, 256));
+        hipLaunchKernelGGL(peak_fit_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                           Fq + l0 * p.nphi, Fu + l0 * p.nphi, idx + l0, n, p.nphi, p.d_phi,
+                           phi_fit ? phi_fit + l0 : nullptr, amp_fit ? amp_fit + l0 : nullptr);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        l0 += n;
+    }
+    return hipSuccess;
+}
 
 hipError_t launch_peak_angle(const rmsynth_plan_s& p, const float* phi_pk, const float* q_pk,
                              const float* u_pk, int64_t nlos, float* chi0, hipStream_t s)

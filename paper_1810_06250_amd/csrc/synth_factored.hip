@@ -88,17 +88,19 @@ __device__ __forceinline__ f32x16_t mfma16(uint4 a, uint4 b, f32x16_t c)
 // LOS-major input, rows are 16-byte aligned; the K-loop is then branch-free.
 // FLAGS: some channel has weight 0; its (zero) rotation then also clears
 // whatever the data hold there, NaN included.
-// PEAKS: the epilogue also reduces |F|^2 of every LOS over the tile's phi and
-// writes one PeakPart per (LOS, half of a phi tile) for peak_merge_kernel,
-// at part[half tile * part_ld + LOS].
-template <int LAYOUT, bool FP16, bool FAST, bool FLAGS, bool PEAKS>
+// PEAKS 1: the epilogue also reduces |F|^2 of every LOS over the tile's phi
+// and writes one PeakPart per (LOS, half of a phi tile) for
+// peak_merge_kernel, at part[half tile * part_ld + LOS].
+// PEAKS 2: F is not stored; the epilogue writes one PeakRec per (LOS, half
+// tile) instead, at rec[half tile * part_ld + LOS], for peak_merge_rec_kernel.
+template <int LAYOUT, bool FP16, bool FAST, bool FLAGS, int PEAKS>
 __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
     const float* __restrict__ Q, const float* __restrict__ U, int64_t nlos, int64_t ld,
     int nchan, const float2* __restrict__ base, const uint4* __restrict__ Thi,
     const uint4* __restrict__ Tlo, int nchan_pad, int nk, int nphi, int tiles_n,
     float* __restrict__ Fq, float* __restrict__ Fu, float* __restrict__ Fabs,
     const float* __restrict__ los_scale, PeakPart* __restrict__ part, int64_t part_ld,
-    uint32_t neg_hi)
+    PeakRec* __restrict__ rec, uint32_t neg_hi)
 {
     // Triple-buffered A tiles (packed data) and T tiles (phase table), in one
     // block so that the epilogue can reuse all of it.
@@ -384,6 +386,7 @@ __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
                 }
             }
     }
+    if constexpr (PEAKS != 2) {
 #pragma unroll
     for (int g = 0; g < 2; ++g)
 #pragma unroll
@@ -417,7 +420,8 @@ __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
                     }
             }
         }
-    if constexpr (PEAKS) {
+    }
+    if constexpr (PEAKS != 0) {
         // |F|^2 of the wave's 64 LOS x 64 phi (columns past the grid: -1) goes
         // through the wave's own 9 KB of the LDS block, which the main
         // loop no longer uses (every wave has passed the last K-step's
@@ -429,6 +433,10 @@ __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
         float best = -1.0f;
         int bk = 0;
         bool bad = false;
+        // PEAKS 2: |F|^2 just before and after the best (prv, nxt) and at the
+        // two ends of the 64 (first, last); -1 where there is none.
+        float prv = -1.0f, nxt = -1.0f, first = -1.0f, last = -1.0f;
+        bool want_next = false;
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb) {
 #pragma unroll
@@ -448,9 +456,21 @@ __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
                 const float mm[4] = {m4.x, m4.y, m4.z, m4.w};
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    bad |= !(mm[e] <= FLT_MAX);
-                    if (mm[e] > best) {
-                        best = mm[e];
+                    const float v = mm[e];
+                    bad |= !(v <= FLT_MAX);
+                    if constexpr (PEAKS == 2) {
+                        if (cb == 0 && q == 0 && e == 0) first = v;
+                        if (want_next) nxt = v;
+                        want_next = false;
+                        if (v > best) {
+                            prv = last;
+                            nxt = -1.0f;
+                            want_next = true;
+                        }
+                        last = v;
+                    }
+                    if (v > best) {
+                        best = v;
                         bk = 32 * cb + 4 * q + e;
                     }
                 }
@@ -458,7 +478,36 @@ __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
             __builtin_amdgcn_wave_barrier();
         }
         const int64_t l = l0 + 64 * wr + lane;
-        if (l < nlos) part[(2 * tn + wc) * part_ld + l] = PeakPart{best, bad ? -2 : n0 + 64 * wc + bk};
+        if constexpr (PEAKS == 1) {
+            if (l < nlos) part[(2 * tn + wc) * part_ld + l] = PeakPart{best, bad ? -2 : n0 + 64 * wc + bk};
+        } else {
+            // Fq, Fu of row `lane` at column bk: each part goes through the
+            // same LDS rows once per 32 columns, and the lane whose column is
+            // in that half picks it up.
+            float pq = 0.0f, pu = 0.0f;
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+                for (int p = 0; p < 2; ++p) {
+#pragma unroll
+                    for (int g = 0; g < 2; ++g)
+#pragma unroll
+                        for (int v = 0; v < 16; ++v) {
+                            const int row = 32 * g + 8 * (v >> 2) + 4 * half + (v & 3);
+                            sm[row * SR + col] = acc[g][p][cb][v];
+                        }
+                    __builtin_amdgcn_wave_barrier();
+                    const float val = sm[lane * SR + (bk & 31)];
+                    if ((bk >> 5) == cb) {
+                        if (p == 0) pq = val;
+                        else pu = val;
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                }
+            if (l < nlos)
+                rec[(2 * tn + wc) * part_ld + l] =
+                    PeakRec{best, bad ? -2 : n0 + 64 * wc + bk, pq, pu, prv, nxt, first, last};
+        }
     }
 }
 
@@ -498,6 +547,64 @@ __global__ void peak_merge_kernel(const PeakPart* __restrict__ part, int nparts,
         if (amp) amp[l] = sqrtf(best);
         if (q_pk) q_pk[l] = Fq[l * nphi + bi];
         if (u_pk) u_pk[l] = Fu[l * nphi + bi];
+    }
+}
+
+// Merge of full records (the transform stored no F): the peak as in
+// peak_merge_kernel, Fq and Fu at the peak from its record, and the sub-grid
+// fit through |F| at idx - 1, idx, idx + 1, a neighbour across a 64-phi
+// boundary being the adjacent record's first or last value.
+__global__ void peak_merge_rec_kernel(const PeakRec* __restrict__ rec, int nparts, int64_t nlos,
+                                      int64_t rec_ld, int nphi, const double* __restrict__ phik,
+                                      int32_t* __restrict__ idx, float* __restrict__ phi_pk,
+                                      float* __restrict__ amp, float* __restrict__ q_pk,
+                                      float* __restrict__ u_pk, float* __restrict__ phi_fit,
+                                      float* __restrict__ amp_fit)
+{
+    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= nlos) return;
+    float best = -1.0f;
+    int bi = -1, bt = -1;
+    bool bad = false;
+    for (int t = 0; t < nparts; ++t) {
+        const PeakRec& r = rec[t * rec_ld + l];
+        const float m = r.m;
+        bad |= r.idx == -2;
+        if (m > best) {
+            best = m;
+            bi = r.idx;
+            bt = t;
+        }
+    }
+    const float nan = __builtin_nanf("");
+    if (bad || bi < 0 || bi >= nphi) {
+        idx[l] = -1;
+        if (phi_pk) phi_pk[l] = nan;
+        if (amp) amp[l] = nan;
+        if (q_pk) q_pk[l] = nan;
+        if (u_pk) u_pk[l] = nan;
+        if (phi_fit) phi_fit[l] = nan;
+        if (amp_fit) amp_fit[l] = nan;
+        return;
+    }
+    const PeakRec r = rec[bt * rec_ld + l];
+    idx[l] = bi;
+    if (phi_pk) phi_pk[l] = (float)phik[bi];
+    if (amp) amp[l] = sqrtf(best);
+    if (q_pk) q_pk[l] = r.q;
+    if (u_pk) u_pk[l] = r.u;
+    if (phi_fit || amp_fit) {
+        float mp = r.prv, mn = r.nxt;
+        if (mp < 0.0f && bt > 0) mp = rec[(bt - 1) * rec_ld + l].last;
+        if (mn < 0.0f && bt + 1 < nparts) mn = rec[(bt + 1) * rec_ld + l].first;
+        const double y0 = mp >= 0.0f ? __builtin_sqrt((double)mp) : __builtin_nan("");
+        const double y2 = mn >= 0.0f ? __builtin_sqrt((double)mn) : __builtin_nan("");
+        const double x0 = bi > 0 ? phik[bi - 1] : __builtin_nan("");
+        const double x2 = bi + 1 < nphi ? phik[bi + 1] : __builtin_nan("");
+        float pf, af;
+        parabola_vertex(x0, y0, phik[bi], __builtin_sqrt((double)best), x2, y2, &pf, &af);
+        if (phi_fit) phi_fit[l] = pf;
+        if (amp_fit) amp_fit[l] = af;
     }
 }
 
@@ -600,11 +707,12 @@ hipError_t launch_t(const rmsynth_plan_s& p, const ExecArgs& a)
     hipLaunchKernelGGL((synth_factored_kernel<L, FP16, F, G, P>), dim3((unsigned)blocks), dim3(256), 0, \
                        a.stream, a.Q, a.U, a.nlos, a.ld, p.nchan, p.d_base, Thi, Tlo,                  \
                        p.nchan_pad, nk, p.nphi, tiles_n, a.Fq, a.Fu, a.Fabs, a.los_scale, a.peak_part,  \
-                       a.peak_part_ld, 0x80000000u)
-#define RMS_LAUNCH_P(L, F, G)                      \
-    do {                                           \
-        if (a.peak_part) RMS_LAUNCH(L, F, G, true); \
-        else RMS_LAUNCH(L, F, G, false);           \
+                       a.peak_part_ld, a.peak_rec, 0x80000000u)
+#define RMS_LAUNCH_P(L, F, G)                         \
+    do {                                              \
+        if (a.peak_rec) RMS_LAUNCH(L, F, G, 2);       \
+        else if (a.peak_part) RMS_LAUNCH(L, F, G, 1); \
+        else RMS_LAUNCH(L, F, G, 0);                  \
     } while (0)
 #define RMS_LAUNCH_G(L, F)                           \
     do {                                             \
@@ -670,6 +778,24 @@ hipError_t launch_peak_merge(const rmsynth_plan_s& p, const PeakPart* part, int6
                            Fu + l0 * p.nphi, idx + l0, phi_pk ? phi_pk + l0 : nullptr,
                            amp ? amp + l0 : nullptr, q_pk ? q_pk + l0 : nullptr,
                            u_pk ? u_pk + l0 : nullptr);
+        if (hipError_t e = hipGetLastError()) return e;
+        l0 += n;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_peak_merge_rec(const rmsynth_plan_s& p, const PeakRec* rec, int64_t rec_ld,
+                                 int64_t nlos, int32_t* idx, float* phi_pk, float* amp,
+                                 float* q_pk, float* u_pk, float* phi_fit, float* amp_fit,
+                                 hipStream_t s)
+{
+    for (int64_t l0 = 0; l0 < nlos;) {
+        const int64_t n = nlos - l0 < max_items(256, 256) ? nlos - l0 : max_items(256, 256);
+        hipLaunchKernelGGL(peak_merge_rec_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                           rec + l0, 2 * p.ftiles, n, rec_ld, p.nphi, p.d_phi, idx + l0,
+                           phi_pk ? phi_pk + l0 : nullptr, amp ? amp + l0 : nullptr,
+                           q_pk ? q_pk + l0 : nullptr, u_pk ? u_pk + l0 : nullptr,
+                           phi_fit ? phi_fit + l0 : nullptr, amp_fit ? amp_fit + l0 : nullptr);
         if (hipError_t e = hipGetLastError()) return e;
         l0 += n;
     }

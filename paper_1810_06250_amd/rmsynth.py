@@ -50,6 +50,15 @@ SIGNATURES = {
     "rmsynth_execute_peaks_workspace_size": (ctypes.c_int, [_P, _I64, _I32, _I32,
                                                             ctypes.POINTER(_SZ)]),
     "rmsynth_peak_angle": (ctypes.c_int, [_P, _P, _P, _P, _I64, _P, _P]),
+    "rmsynth_search": (ctypes.c_int, [_P, _P, _P, _I64, _I32, _I32, _P, _P, _P, _P, _P, _P, _P, _P,
+                                      _SZ, _P]),
+    "rmsynth_search_workspace_size": (ctypes.c_int, [_P, _I64, _I32, _I32, ctypes.POINTER(_SZ)]),
+    "rmsynth_peak_fit": (ctypes.c_int, [_P, _P, _P, _P, _I64, _P, _P, _P]),
+    "rmsynth_adjoint": (ctypes.c_int, [_P, _P, _P, _I64, _I32, _P, _P, _P, _SZ, _P]),
+    "rmsynth_adjoint_workspace_size": (ctypes.c_int, [_P, _I64, _I32, ctypes.POINTER(_SZ)]),
+    "rmsynth_rmclean": (ctypes.c_int, [_P, _P, _P, _I64, ctypes.c_float, ctypes.c_float, _I32, _D,
+                                       _P, _P, _P, _P, _P, _P, _P, _P, _SZ, _P]),
+    "rmsynth_rmclean_workspace_size": (ctypes.c_int, [_P, ctypes.POINTER(_SZ)]),
     "rmsynth_destroy": (None, [_P]),
     "rmsynth_last_error": (ctypes.c_char_p, []),
     "rmsynth_version": (ctypes.c_char_p, []),
@@ -283,6 +292,96 @@ def rmsynth_execute_peaks(plan, Q, U, nlos: int, layout: int, precision: int, Fq
         int(workspace_bytes), _stream(stream)))
 
 
+def rmsynth_search_workspace_size(plan, nlos: int, layout: int, precision: int) -> int:
+    b = ctypes.c_size_t()
+    _check("rmsynth_search_workspace_size", load_library().rmsynth_search_workspace_size(
+        plan, int(nlos), int(layout), int(precision), ctypes.byref(b)))
+    return b.value
+
+
+def rmsynth_search(plan, Q, U, nlos: int, layout: int, precision: int, idx, phi_pk=None, amp=None,
+                   q_pk=None, u_pk=None, phi_fit=None, amp_fit=None, workspace=None,
+                   workspace_bytes: int = 0, stream=None):
+    import torch
+    nchan, _ = _plan_dims(plan)
+    _need_cube(Q, U, int(nlos), nchan, layout)
+    for t, name in ((idx, "idx"), (phi_pk, "phi_pk"), (amp, "amp"), (q_pk, "q_pk"), (u_pk, "u_pk"),
+                    (phi_fit, "phi_fit"), (amp_fit, "amp_fit")):
+        _need(t, name, int(nlos))
+    _need_bytes(workspace, int(workspace_bytes))
+    f32 = torch.float32
+    _check("rmsynth_search", load_library().rmsynth_search(
+        plan, _dev(Q, "Q", f32), _dev(U, "U", f32), int(nlos), int(layout), int(precision),
+        _dev(idx, "idx", torch.int32), _dev(phi_pk, "phi_pk", f32), _dev(amp, "amp", f32),
+        _dev(q_pk, "q_pk", f32), _dev(u_pk, "u_pk", f32), _dev(phi_fit, "phi_fit", f32),
+        _dev(amp_fit, "amp_fit", f32), _dev(workspace, "workspace"), int(workspace_bytes),
+        _stream(stream)))
+
+
+def rmsynth_peak_fit(plan, Fq, Fu, idx, nlos: int, phi_fit=None, amp_fit=None, stream=None):
+    import torch
+    _, nphi = _plan_dims(plan)
+    _need_rows(Fq, "Fq", int(nlos), nphi)
+    _need_rows(Fu, "Fu", int(nlos), nphi)
+    for t, name in ((idx, "idx"), (phi_fit, "phi_fit"), (amp_fit, "amp_fit")):
+        _need(t, name, int(nlos))
+    f32 = torch.float32
+    _check("rmsynth_peak_fit", load_library().rmsynth_peak_fit(
+        plan, _dev(Fq, "Fq", f32), _dev(Fu, "Fu", f32), _dev(idx, "idx", torch.int32), int(nlos),
+        _dev(phi_fit, "phi_fit", f32), _dev(amp_fit, "amp_fit", f32), _stream(stream)))
+
+
+def rmsynth_adjoint_workspace_size(plan, nlos: int, precision: int) -> int:
+    b = ctypes.c_size_t()
+    _check("rmsynth_adjoint_workspace_size", load_library().rmsynth_adjoint_workspace_size(
+        plan, int(nlos), int(precision), ctypes.byref(b)))
+    return b.value
+
+
+def rmsynth_adjoint(plan, Cq, Cu, nlos: int, precision: int, Pq, Pu, workspace=None,
+                    workspace_bytes: int = 0, stream=None):
+    import torch
+    nchan, nphi = _plan_dims(plan)
+    if Cq is not None and Cu is not None and tuple(Cq.shape) != tuple(Cu.shape):
+        raise ValueError(f"Cq {tuple(Cq.shape)} and Cu {tuple(Cu.shape)} differ in shape")
+    for t, name in ((Cq, "Cq"), (Cu, "Cu")):
+        _need_rows(t, name, int(nlos), nphi)
+    for t, name in ((Pq, "Pq"), (Pu, "Pu")):
+        _need_rows(t, name, int(nlos), nchan)
+    _need_bytes(workspace, int(workspace_bytes))
+    f32 = torch.float32
+    _check("rmsynth_adjoint", load_library().rmsynth_adjoint(
+        plan, _dev(Cq, "Cq", f32), _dev(Cu, "Cu", f32), int(nlos), int(precision),
+        _dev(Pq, "Pq", f32), _dev(Pu, "Pu", f32), _dev(workspace, "workspace"),
+        int(workspace_bytes), _stream(stream)))
+
+
+def rmsynth_rmclean_workspace_size(plan) -> int:
+    b = ctypes.c_size_t()
+    _check("rmsynth_rmclean_workspace_size", load_library().rmsynth_rmclean_workspace_size(
+        plan, ctypes.byref(b)))
+    return b.value
+
+
+def rmsynth_rmclean(plan, Fq, Fu, nlos: int, gain: float, cutoff: float, max_iter: int,
+                    fwhm: float, rq, ru, cq, cu, Rq=None, Ru=None, niter=None, workspace=None,
+                    workspace_bytes: int = 0, stream=None):
+    import torch
+    _, nphi = _plan_dims(plan)
+    for t, name in ((Fq, "Fq"), (Fu, "Fu"), (rq, "rq"), (ru, "ru"), (cq, "cq"), (cu, "cu"),
+                    (Rq, "Rq"), (Ru, "Ru")):
+        _need_rows(t, name, int(nlos), nphi)
+    _need(niter, "niter", int(nlos))
+    _need_bytes(workspace, int(workspace_bytes))
+    f32 = torch.float32
+    _check("rmsynth_rmclean", load_library().rmsynth_rmclean(
+        plan, _dev(Fq, "Fq", f32), _dev(Fu, "Fu", f32), int(nlos), float(gain), float(cutoff),
+        int(max_iter), float(fwhm), _dev(rq, "rq", f32), _dev(ru, "ru", f32), _dev(cq, "cq", f32),
+        _dev(cu, "cu", f32), _dev(Rq, "Rq", f32), _dev(Ru, "Ru", f32),
+        _dev(niter, "niter", torch.int32), _dev(workspace, "workspace"), int(workspace_bytes),
+        _stream(stream)))
+
+
 def rmsynth_destroy(plan):
     if plan:
         load_library().rmsynth_destroy(plan)
@@ -514,6 +613,61 @@ class Plan:
         rmsynth_execute_peaks(self.handle, Q, U, nlos, layout, precision, Fq, Fu, Fa, out["idx"],
                               out["phi_pk"], out["amp"], out["q_pk"], out["u_pk"], ws, nb)
         return Fq, Fu, Fa, out
+
+    def search(self, Q, U, layout: int = RMSYNTH_LOS_MAJOR, precision: int = RMSYNTH_FP32,
+               workspace_bytes: Optional[int] = None):
+        """Peaks and sub-grid peaks without storing F (rmsynth_search).  A
+        workspace_bytes below the whole call's need runs it in LOS batches."""
+        import torch
+        nlos = Q.shape[0] if layout == RMSYNTH_LOS_MAJOR else Q.shape[1]
+        dev = Q.device
+        out = dict(idx=torch.empty(nlos, dtype=torch.int32, device=dev))
+        for k in ("phi_pk", "amp", "q_pk", "u_pk", "phi_fit", "amp_fit"):
+            out[k] = torch.empty(nlos, dtype=torch.float32, device=dev)
+        nb = rmsynth_search_workspace_size(self.handle, nlos, layout, precision)
+        if workspace_bytes is not None:
+            nb = int(workspace_bytes)
+        ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=dev)
+        rmsynth_search(self.handle, Q, U, nlos, layout, precision, out["idx"], out["phi_pk"],
+                       out["amp"], out["q_pk"], out["u_pk"], out["phi_fit"], out["amp_fit"], ws, nb)
+        return out
+
+    def adjoint(self, Cq, Cu, precision: int = RMSYNTH_FP32):
+        """Spectra [nlos][nchan] of Faraday-depth components [nlos][nphi]
+        (rmsynth_adjoint)."""
+        import torch
+        nlos = Cq.shape[0]
+        Pq = torch.empty((nlos, self.nchan), dtype=torch.float32, device=Cq.device)
+        Pu = torch.empty_like(Pq)
+        nb = rmsynth_adjoint_workspace_size(self.handle, nlos, precision)
+        ws = torch.empty(nb, dtype=torch.uint8, device=Cq.device) if nb else None
+        rmsynth_adjoint(self.handle, Cq, Cu, nlos, precision, Pq, Pu, ws, nb)
+        return Pq, Pu
+
+    def rmclean(self, Fq, Fu, gain: float, cutoff: float, max_iter: int,
+                fwhm: float = float("nan"), restore: bool = True):
+        """RM-CLEAN of the spectra (rmsynth_rmclean): dict of resid (rq, ru),
+        components (cq, cu), restored (Rq, Ru) and niter."""
+        import torch
+        nlos = Fq.shape[0]
+        o = {k: torch.empty_like(Fq) for k in ("rq", "ru", "cq", "cu")}
+        if restore:
+            o["Rq"], o["Ru"] = torch.empty_like(Fq), torch.empty_like(Fq)
+        o["niter"] = torch.empty(nlos, dtype=torch.int32, device=Fq.device)
+        nb = rmsynth_rmclean_workspace_size(self.handle)
+        ws = torch.empty(nb, dtype=torch.uint8, device=Fq.device)
+        rmsynth_rmclean(self.handle, Fq, Fu, nlos, gain, cutoff, max_iter, fwhm, o["rq"], o["ru"],
+                        o["cq"], o["cu"], o.get("Rq"), o.get("Ru"), o["niter"], ws, nb)
+        return o
+
+    def peak_fit(self, Fq, Fu, idx):
+        """Sub-grid peak (rmsynth_peak_fit) around the indices idx."""
+        import torch
+        nlos = Fq.shape[0]
+        pf = torch.empty(nlos, dtype=torch.float32, device=Fq.device)
+        af = torch.empty_like(pf)
+        rmsynth_peak_fit(self.handle, Fq, Fu, idx, nlos, pf, af)
+        return pf, af
 
     def peak_angle(self, pk):
         """Polarization angle at each LOS's peak referred to lambda^2 = 0

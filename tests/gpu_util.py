@@ -1,7 +1,10 @@
-"""Helpers shared by the GPU parity tests (no arithmetic of the method here)."""
+"""Helpers shared by the GPU parity tests: tolerances and marshalling (the
+method's arithmetic is the oracle's)."""
 import sys
 
 import numpy as np
+
+import oracle
 
 PREC_TOL = {  # per-LOS bound on max_k |F_gpu - F_oracle| / max_k |F_oracle|
     "fp32": 1e-5,
@@ -36,3 +39,25 @@ def host(t):
     import torch
     torch.cuda.synchronize()
     return t.detach().cpu().numpy()
+
+
+def fit_bar(Fq, Fu, phi, idx, dy):
+    """Largest change of the parabola's vertex (phi, amp) when each of the
+    three amplitudes around idx moves by up to dy[l] (corners of the box),
+    doubled.  Rows whose peak sits at a grid end only move amp (by dy)."""
+    Fq, Fu = np.asarray(Fq, np.float64), np.asarray(Fu, np.float64)
+    rows = np.arange(len(idx))
+    nphi = Fq.shape[1]
+    k = np.clip(idx, 1, nphi - 2)
+    y = [np.hypot(Fq[rows, k + d], Fu[rows, k + d]) for d in (-1, 0, 1)]
+    x = [phi[k + d] for d in (-1, 0, 1)]
+    p0, a0 = oracle.peak_fit(y[0], y[1], y[2], *x)
+    dp, da = np.zeros(len(idx)), np.zeros(len(idx))
+    for s0 in (-1, 1):
+        for s1 in (-1, 1):
+            for s2 in (-1, 1):
+                p, a = oracle.peak_fit(y[0] + s0 * dy, y[1] + s1 * dy, y[2] + s2 * dy, *x)
+                dp = np.maximum(dp, np.abs(p - p0))
+                da = np.maximum(da, np.abs(a - a0))
+    edge = (idx == 0) | (idx == nphi - 1)
+    return np.where(edge, 0.0, 2 * dp), np.where(edge, 2 * dy, 2 * da)

@@ -1,0 +1,172 @@
+"""Spectrum synthesis (rmsynth_adjoint) against the FP64 oracle, through the C ABI.
+
+P_lj = sum_k C_lk exp(+2i phi_k (lambda_j^2 - lambda0^2)): eq. (4) as a sum
+over the grid components, referred to lambda0^2 as eq. (11) refers F.
+Bar: per LOS, max_j |P_gpu - P_oracle| / max_j |P_oracle| <= 1e-5 for FP32
+and the split precisions (the same per-LOS rule as the forward transform)
+when many components add up.  With a few components (sparse C, a single
+thin screen) nothing averages the split's rounding out: there, as on the
+forward transform's grids of a few phi, the error is taken relative to
+max(max_j |P|, sqrt(sum_k |C_k|^2)) and the bfloat16 split is held to its
+per-product bound 3 x 2^-16 (FP32 and FP16 stay at 1e-5).
+Also: a single component is a Faraday-thin screen (eqs. (1), (3)) exactly,
+the GPU forward and adjoint transforms satisfy <F(P), C> = <P, K w A(C)>, and
+the phase tables take the factored path when the channels are uniform in
+lambda^2 (FP16 allowed only there).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1810_06250_amd as rs
+from synthetic import WORKLOADS, band_lambda2, thin_spectrum, LOS_MAJOR
+from gpu_util import PREC_TOL, SCALE_TOL, dev32, host, note
+
+pytestmark = pytest.mark.gpu
+
+PRECS = {"fp32": rs.RMSYNTH_FP32, "bf16x3": rs.RMSYNTH_SPLIT_BF16, "fp16x3": rs.RMSYNTH_SPLIT_FP16}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    rs.load_library()
+    oracle.build(force=False)
+
+
+def _components(rng, nlos, nphi, kind):
+    if kind == "dense":
+        return rng.standard_normal((nlos, nphi)) + 1j * rng.standard_normal((nlos, nphi))
+    C = np.zeros((nlos, nphi), complex)
+    for l in range(nlos):                 # a few clean-component-like spikes
+        k = rng.choice(nphi, size=min(nphi, rng.integers(1, 6)), replace=False)
+        C[l, k] = rng.uniform(0.01, 0.1, k.size) * np.exp(1j * rng.uniform(0, 2 * np.pi, k.size))
+    return C
+
+
+def _check(plan, C, lam, w, phi, prec, tol, few=False):
+    C32 = C.real.astype(np.float32) + 1j * C.imag.astype(np.float32)
+    Pq, Pu = plan.adjoint(dev32(C32.real), dev32(C32.imag), PRECS[prec])
+    gq, gu = host(Pq), host(Pu)
+    rq, ru = oracle.adjoint(C32.real, C32.imag, lam, w, phi)
+    floor = np.sqrt(np.sum(np.abs(C32.astype(np.complex128)) ** 2, axis=1)) if few else None
+    err = oracle.per_los_error(gq, gu, rq, ru, floor=floor)
+    note(f"  adjoint {prec}: max per-LOS error {err.max():.3e}")
+    assert np.all(np.isfinite(err)) and err.max() <= tol, err.max()
+    return gq, gu
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("band,nlos,nphi,kind", [
+    ("c1", 300, 201, "dense"), ("c1", 129, 7, "dense"), ("c2", 200, 1001, "sparse"),
+    ("c3", 130, 2001, "dense"), ("c3", 64, 333, "sparse"), ("c4", 70, 4001, "sparse"),
+    ("c5", 257, 1201, "dense")])
+def test_adjoint_matches_oracle(prec, band, nlos, nphi, kind):
+    note(f"adjoint {band} {nlos}x{nphi} {kind} {prec}")
+    wl = WORKLOADS[band]
+    lam, w = wl.lambda2(), wl.weights()
+    span = float(np.max(np.abs(wl.phi())))
+    phi = np.linspace(-span, span, nphi)
+    plan = rs.Plan(lam, w, phi)
+    rng = np.random.default_rng(nlos + nphi)
+    few = kind == "sparse"
+    _check(plan, _components(rng, nlos, nphi, kind), lam, w, phi, prec,
+           SCALE_TOL[prec] if few else PREC_TOL[prec], few=few)
+
+
+def test_adjoint_on_an_irregular_grid():
+    note("adjoint irregular grid")
+    lam = band_lambda2(700.0, 1800.0, 150)
+    w = np.ones(150)
+    phi = np.sort(np.random.default_rng(3).uniform(-500, 500, 700))
+    plan = rs.Plan(lam, w, phi)
+    C = _components(np.random.default_rng(4), 100, phi.size, "dense")
+    for prec in ("fp32", "bf16x3"):
+        _check(plan, C, lam, w, phi, prec, PREC_TOL[prec])
+
+
+@pytest.mark.parametrize("prec", list(PRECS))
+def test_channels_uniform_in_lambda2_take_the_factored_tables(prec):
+    """lambda^2 on a uniform grid: the exchanged axes make the output grid
+    uniform, so the factored kernels (and FP16) serve the adjoint too."""
+    note(f"adjoint uniform lambda^2 {prec}")
+    lam = np.linspace(0.03, 0.19, 300)
+    w = np.ones(300)
+    w[[7, 100]] = 0.0                       # weights do not enter the adjoint
+    phi = np.linspace(-1000, 1000, 1501)
+    plan = rs.Plan(lam, w, phi)
+    C = _components(np.random.default_rng(8), 200, phi.size, "dense")
+    _check(plan, C, lam, w, phi, prec, PREC_TOL[prec])
+
+
+def test_fp16_needs_channels_uniform_in_lambda2():
+    import torch
+    wl = WORKLOADS["c1"]
+    plan = rs.Plan(wl.lambda2(), wl.weights(), wl.phi())
+    C = torch.zeros((4, plan.nphi), dtype=torch.float32, device="cuda")
+    P = torch.empty((4, plan.nchan), dtype=torch.float32, device="cuda")
+    with pytest.raises(rs.RmsynthError) as ei:
+        rs.rmsynth_adjoint(plan.handle, C, C, 4, rs.RMSYNTH_SPLIT_FP16, P, P)
+    assert ei.value.code == rs.RMSYNTH_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_single_component_is_a_thin_screen(prec):
+    """C_k0 = P0 exp(2i(chi0 + phi_k0 lambda0^2)) gives the thin screen
+    P0 exp(2i(chi0 + phi_k0 lambda^2)) (eqs. (1), (3)) in every channel."""
+    note(f"adjoint thin screen {prec}")
+    wl = WORKLOADS["c4"]
+    lam, w, phi = wl.lambda2(), wl.weights(), wl.phi()
+    plan = rs.Plan(lam, w, phi)
+    K, l0 = oracle.plan(lam, w)
+    rng = np.random.default_rng(12)
+    n = 256
+    ks = rng.integers(0, phi.size, n)
+    P0, chi0 = rng.uniform(0.01, 0.1, n), rng.uniform(0, np.pi, n)
+    C = np.zeros((n, phi.size), complex)
+    C[np.arange(n), ks] = P0 * np.exp(2j * (chi0 + phi[ks] * l0))
+    C32 = C.real.astype(np.float32) + 1j * C.imag.astype(np.float32)
+    Pq, Pu = (host(t) for t in plan.adjoint(dev32(C32.real), dev32(C32.imag), PRECS[prec]))
+    want = thin_spectrum(lam, np.abs(C32[np.arange(n), ks]), phi[ks],
+                         0.5 * np.angle(C32[np.arange(n), ks]) - phi[ks] * l0)
+    err = np.max(np.abs(Pq + 1j * Pu - want), axis=1) / np.abs(want).max(axis=1)
+    note(f"  thin screens: max error {err.max():.3e}")
+    assert err.max() <= SCALE_TOL[prec]     # one component: nothing averages
+
+
+def test_adjoint_identity_on_the_gpu():
+    """<F(P), C> = <P, K w A(C)> with the GPU's forward and adjoint
+    transforms (FP32), to 1e-5 of ||F(P)|| ||C|| per LOS."""
+    note("adjoint identity")
+    wl = WORKLOADS["c2"]
+    lam, w, phi = wl.lambda2(), wl.weights(), wl.phi()
+    plan = rs.Plan(lam, w, phi)
+    K, _ = oracle.plan(lam, w)
+    rng = np.random.default_rng(6)
+    n = 64
+    P = (rng.standard_normal((n, lam.size)) + 1j * rng.standard_normal((n, lam.size))).astype(np.complex64)
+    C = (rng.standard_normal((n, phi.size)) + 1j * rng.standard_normal((n, phi.size))).astype(np.complex64)
+    Fq, Fu, _ = plan.execute(dev32(P.real), dev32(P.imag), LOS_MAJOR, rs.RMSYNTH_FP32)
+    Aq, Au = plan.adjoint(dev32(C.real), dev32(C.imag), rs.RMSYNTH_FP32)
+    F = host(Fq).astype(np.float64) + 1j * host(Fu)
+    A = host(Aq).astype(np.float64) + 1j * host(Au)
+    lhs = np.sum(np.conj(F) * C, axis=1)
+    rhs = np.sum(np.conj(P) * (K * w) * A, axis=1)
+    scale = np.linalg.norm(F, axis=1) * np.linalg.norm(C, axis=1)
+    assert np.max(np.abs(lhs - rhs) / scale) <= 1e-5
+
+
+def test_nonfinite_component_poisons_only_its_los():
+    wl = WORKLOADS["c1"]
+    lam, w, phi = wl.lambda2(), wl.weights(), wl.phi()
+    plan = rs.Plan(lam, w, phi)
+    C = np.random.default_rng(1).standard_normal((10, phi.size)).astype(np.float32)
+    a = [host(t) for t in plan.adjoint(dev32(C), dev32(C), rs.RMSYNTH_SPLIT_BF16)]
+    C[4, 17] = np.nan
+    b = [host(t) for t in plan.adjoint(dev32(C), dev32(C), rs.RMSYNTH_SPLIT_BF16)]
+    assert np.all(~np.isfinite(b[0][4]))
+    keep = np.arange(10) != 4
+    np.testing.assert_array_equal(b[0][keep], a[0][keep])
+    np.testing.assert_array_equal(b[1][keep], a[1][keep])
