@@ -198,6 +198,31 @@ int rmsynth_search_workspace_size(rmsynth_plan_t plan, int64_t nlos, int32_t lay
                                   int32_t precision, size_t* bytes);
 
 /*
+ * rmsynth_search_noalloc -- rmsynth_search for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same arguments without a workspace,
+ * the same results bit for bit.  Its workspace is a fixed array of
+ * rmsynth_search_noalloc_scratch_bytes() (64 MiB) inside the library, one
+ * per device, held until the process ends; the LOS run in batches that fit
+ * it.  The call itself allocates nothing (no hipMalloc, hipFree or
+ * allocating library routine).
+ *   All calls on one device share that device's array: calls that overlap
+ *   on a device (several streams or threads) race and must be serialised by
+ *   the caller.  No part of the array has to start at zero.
+ * Errors as rmsynth_search; EINVAL when one batch of 128 LOS does not fit
+ * the array (only the unfused paths, which hold F of a batch: nphi above
+ * 65536 on a non-uniform grid or at FP32).
+ */
+int rmsynth_search_noalloc(rmsynth_plan_t plan, const float* Q, const float* U, int64_t nlos,
+                           int32_t layout, int32_t precision, int32_t* idx, float* phi_pk,
+                           float* amp, float* q_pk, float* u_pk, float* phi_fit, float* amp_fit,
+                           void* stream);
+
+/* rmsynth_search_noalloc_scratch_bytes -- size of rmsynth_search_noalloc's
+ * per-device array. */
+size_t rmsynth_search_noalloc_scratch_bytes(void);
+
+/*
  * rmsynth_adjoint -- spectra from Faraday-depth components on the plan's
  * grid: eq. (4) (P(lambda^2) as the integral of F(phi) exp(2i phi lambda^2))
  * as a sum over the grid, referred to lambda0^2 as eq. (11) refers F:

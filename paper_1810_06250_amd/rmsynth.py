@@ -53,6 +53,9 @@ SIGNATURES = {
     "rmsynth_search": (ctypes.c_int, [_P, _P, _P, _I64, _I32, _I32, _P, _P, _P, _P, _P, _P, _P, _P,
                                       _SZ, _P]),
     "rmsynth_search_workspace_size": (ctypes.c_int, [_P, _I64, _I32, _I32, ctypes.POINTER(_SZ)]),
+    "rmsynth_search_noalloc": (ctypes.c_int, [_P, _P, _P, _I64, _I32, _I32, _P, _P, _P, _P, _P, _P,
+                                              _P, _P]),
+    "rmsynth_search_noalloc_scratch_bytes": (_SZ, []),
     "rmsynth_peak_fit": (ctypes.c_int, [_P, _P, _P, _P, _I64, _P, _P, _P]),
     "rmsynth_adjoint": (ctypes.c_int, [_P, _P, _P, _I64, _I32, _P, _P, _P, _SZ, _P]),
     "rmsynth_adjoint_workspace_size": (ctypes.c_int, [_P, _I64, _I32, ctypes.POINTER(_SZ)]),
@@ -316,6 +319,27 @@ def rmsynth_search(plan, Q, U, nlos: int, layout: int, precision: int, idx, phi_
         _dev(q_pk, "q_pk", f32), _dev(u_pk, "u_pk", f32), _dev(phi_fit, "phi_fit", f32),
         _dev(amp_fit, "amp_fit", f32), _dev(workspace, "workspace"), int(workspace_bytes),
         _stream(stream)))
+
+
+def rmsynth_search_noalloc(plan, Q, U, nlos: int, layout: int, precision: int, idx, phi_pk=None,
+                           amp=None, q_pk=None, u_pk=None, phi_fit=None, amp_fit=None,
+                           stream=None):
+    import torch
+    nchan, _ = _plan_dims(plan)
+    _need_cube(Q, U, int(nlos), nchan, layout)
+    for t, name in ((idx, "idx"), (phi_pk, "phi_pk"), (amp, "amp"), (q_pk, "q_pk"), (u_pk, "u_pk"),
+                    (phi_fit, "phi_fit"), (amp_fit, "amp_fit")):
+        _need(t, name, int(nlos))
+    f32 = torch.float32
+    _check("rmsynth_search_noalloc", load_library().rmsynth_search_noalloc(
+        plan, _dev(Q, "Q", f32), _dev(U, "U", f32), int(nlos), int(layout), int(precision),
+        _dev(idx, "idx", torch.int32), _dev(phi_pk, "phi_pk", f32), _dev(amp, "amp", f32),
+        _dev(q_pk, "q_pk", f32), _dev(u_pk, "u_pk", f32), _dev(phi_fit, "phi_fit", f32),
+        _dev(amp_fit, "amp_fit", f32), _stream(stream)))
+
+
+def rmsynth_search_noalloc_scratch_bytes() -> int:
+    return int(load_library().rmsynth_search_noalloc_scratch_bytes())
 
 
 def rmsynth_peak_fit(plan, Fq, Fu, idx, nlos: int, phi_fit=None, amp_fit=None, stream=None):
