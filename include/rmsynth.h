@@ -253,6 +253,26 @@ int rmsynth_adjoint_workspace_size(rmsynth_plan_t plan, int64_t nlos, int32_t pr
                                    size_t* bytes);
 
 /*
+ * rmsynth_execute_nufft -- the Faraday-depth transform of eq. (11) on a
+ * uniform phi grid evaluated by a non-uniform FFT, the FFT evaluation the
+ * paper proposes in place of the direct sums of eqs. (15)-(16) (Section 4):
+ * with phi_k = phi_c + (k - kc) dphi (kc = nphi / 2), F is a type-1
+ * non-uniform DFT of c_j = K w_j P_j exp(-2i a_j phi_c) at the points
+ * x_j = 2 a_j dphi (mod 2 pi), computed by gridding the c_j onto the
+ * smallest power-of-two grid n >= 2 nphi with an exponential-of-semicircle
+ * kernel 8 cells wide, an n-point FFT (FP32) and division by the kernel's
+ * Fourier transform.  An approximation of eq. (11): about 1e-6 of max|F|
+ * per LOS (the kernel width's truncation below 1e-7, the rest FP32).
+ *   Q, U     [nlos][nchan] device float (LOS-major).
+ *   Fq, Fu   [nlos][nphi] device float; Fabs [nlos][nphi] or NULL.
+ * Needs a uniform phi grid with n <= 8192 (nphi <= 4096), nchan <= 4096 and
+ * (n + nchan) * 8 bytes of LDS per workgroup; EUNSUPPORTED otherwise.  A LOS
+ * whose unflagged channels hold a non-finite value gets non-finite outputs.
+ */
+int rmsynth_execute_nufft(rmsynth_plan_t plan, const float* Q, const float* U, int64_t nlos,
+                          float* Fq, float* Fu, float* Fabs, void* stream);
+
+/*
  * rmsynth_rmclean -- RM-CLEAN of each LOS's Faraday spectrum: the
  * deconvolution by the RMSF R(phi) of eq. (12) that Section 2.2 names (and the
  * paper leaves unsupported, Section 4), as Hogbom's iteration on a uniform

@@ -45,7 +45,8 @@ void free_plan(rmsynth_plan_s* p)
     if (!p) return;
     free_plan(p->adj);
     void* bufs[] = {p->d_b, p->d_lambda2, p->d_w, p->d_phi, p->d_base, p->d_Tbf[0], p->d_Tbf[1],
-                    p->d_Thf[0], p->d_Thf[1]};
+                    p->d_Thf[0], p->d_Thf[1], p->d_nufft_rot, p->d_nufft_off, p->d_nufft_ej,
+                    p->d_nufft_ew, p->d_nufft_tw, p->d_nufft_deconv};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     delete p;
@@ -223,6 +224,10 @@ int rmsynth_plan(const double* lambda2, const double* weights, int32_t nchan, co
     p->uniform = detect_uniform(phi, nphi, amax, &p->phi0, &p->dphi);
     if (p->uniform) {
         if (int rc = build_factor_tables(p)) {
+            free_plan(p);
+            return rc;
+        }
+        if (int rc = build_nufft_tables(p, lambda2, weights)) {
             free_plan(p);
             return rc;
         }
@@ -577,6 +582,29 @@ int rmsynth_adjoint(rmsynth_plan_t p, const float* Cq, const float* Cu, int64_t 
     if (int rc = run_batched(p->adj, Mode::Execute, Cq, Cu, nlos, RMSYNTH_LOS_MAJOR, precision, Pq, Pu,
                              nullptr, PeakOut{}, workspace, workspace_bytes, (hipStream_t)stream, who))
         return rc;
+    return rms_ok();
+}
+
+int rmsynth_execute_nufft(rmsynth_plan_t p, const float* Q, const float* U, int64_t nlos,
+                          float* Fq, float* Fu, float* Fabs, void* stream)
+{
+    const char* who = "rmsynth_execute_nufft";
+    if (!p) return rms_fail(RMSYNTH_EINVAL, "%s: plan is NULL", who);
+    if (nlos < 0) return rms_fail(RMSYNTH_EINVAL, "%s: nlos=%lld", who, (long long)nlos);
+    if (!p->nufft_n)
+        return rms_fail(RMSYNTH_EUNSUPPORTED, "%s: needs a uniform phi grid of at most %d values and at most "
+                        "%d channels", who, kNufftMaxGrid / 2, kNufftMaxChan);
+    if (nlos == 0) return rms_ok();
+    if (!Q || !U || !Fq || !Fu) return rms_fail(RMSYNTH_EINVAL, "%s: NULL buffer", who);
+    if (int rc = check_device(p)) return rc;
+    int lds_max = 0;
+    hipError_t e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device);
+    if (e != hipSuccess) return rms_hip_fail(e, "hipDeviceGetAttribute");
+    if (nufft_lds_bytes(*p) > (size_t)lds_max)
+        return rms_fail(RMSYNTH_EUNSUPPORTED, "%s: %zu bytes of LDS needed, the device offers %d", who,
+                        nufft_lds_bytes(*p), lds_max);
+    e = launch_nufft(*p, Q, U, nlos, Fq, Fu, Fabs, (hipStream_t)stream);
+    if (e != hipSuccess) return rms_hip_fail(e, "rmsynth_execute_nufft launch");
     return rms_ok();
 }
 

@@ -47,7 +47,24 @@ struct rmsynth_plan_s {
     // The adjoint transform's plan (axes exchanged, see build_adjoint_plan);
     // owned, NULL inside an adjoint plan itself.
     rmsynth_plan_s* adj;
+    // NUFFT evaluation (uniform grids with nufft_n <= kNufftMaxGrid; nufft_n
+    // = 0 otherwise): tables of nufft_plan.cpp.
+    int32_t nufft_n, nufft_kc;
+    float2* d_nufft_rot;    // [nchan]
+    int* d_nufft_off;       // [n + 1]
+    int* d_nufft_ej;        // [entries] channel
+    float* d_nufft_ew;      // [entries] kernel weight
+    float2* d_nufft_tw;     // [n]
+    float* d_nufft_deconv;  // [nphi]
 };
+
+constexpr int kNufftWidth = 8;       // kernel width in grid cells
+constexpr int kNufftMaxGrid = 8192;  // largest grid (LDS: 8 bytes per point)
+constexpr int kNufftMaxChan = 4096;  // channels staged in LDS
+int build_nufft_tables(rmsynth_plan_s* p, const double* lambda2, const double* weights);
+size_t nufft_lds_bytes(const rmsynth_plan_s& p);
+hipError_t launch_nufft(const rmsynth_plan_s& p, const float* Q, const float* U, int64_t nlos,
+                        float* Fq, float* Fu, float* Fabs, hipStream_t s);
 
 constexpr int kFactorTile = 128;  // phi per tile of the factored kernels
 

@@ -25,7 +25,10 @@
 
 namespace {
 
-constexpr int kWaves = 8;  // LOS per workgroup
+// LOS (waves) per workgroup: 8, or 4 for the widest layout (64 elements per
+// lane), whose one wave per SIMD may then use the full register file.
+template <int E>
+constexpr int waves_of() { return E >= 64 ? 4 : 8; }
 
 // R((m - (N-1)) dphi) = K sum_j w_j exp(-2i x a_j) and G at the same offsets.
 __global__ void rmclean_tables_kernel(const double* __restrict__ bj, const float* __restrict__ wj,
@@ -50,7 +53,7 @@ __global__ void rmclean_tables_kernel(const double* __restrict__ bj, const float
 }
 
 template <int E>
-__global__ __launch_bounds__(64 * kWaves) void rmclean_kernel(
+__global__ __launch_bounds__(64 * waves_of<E>()) void rmclean_kernel(
     const float* Fq, const float* Fu, int64_t nlos, int N, const float2* __restrict__ R2g,
     const float* __restrict__ Gg, float gain, float cutoff, int max_iter, float* rq, float* ru,
     float* __restrict__ cq, float* __restrict__ cu, float* __restrict__ Rq, float* __restrict__ Ru,
@@ -63,21 +66,29 @@ __global__ __launch_bounds__(64 * kWaves) void rmclean_kernel(
     for (int i = threadIdx.x; i < 2 * N - 1; i += blockDim.x) R2[i] = R2g[i];
     __syncthreads();
     const int lane = threadIdx.x & 63;
-    const int64_t l = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+    const int64_t l = (int64_t)blockIdx.x * waves_of<E>() + (threadIdx.x >> 6);
     if (l >= nlos) return;  // uniform per wave; no block barrier follows
     const int64_t row = l * N;
 
+    // Elements past the grid (k >= N) hold 0, are never picked (|r|^2 taken
+    // as -1) and never stored; their table index is clamped into the table.
+    // The loops over the register arrays are written without branches (loads
+    // from clamped addresses, selects), which keeps the arrays in registers.
     float xr[E], xi[E];
     bool bad = false;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int k = 64 * e + lane;
-        xr[e] = 0.0f;
-        xi[e] = 0.0f;
+        const int kc = k < N ? k : N - 1;
+        const float a = Fq[row + kc], b = Fu[row + kc];
+        xr[e] = k < N ? a : 0.0f;
+        xi[e] = k < N ? b : 0.0f;
+        bad |= !(__builtin_fabsf(xr[e]) <= FLT_MAX && __builtin_fabsf(xi[e]) <= FLT_MAX);
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int k = 64 * e + lane;
         if (k < N) {
-            xr[e] = Fq[row + k];
-            xi[e] = Fu[row + k];
-            bad |= !(__builtin_fabsf(xr[e]) <= FLT_MAX && __builtin_fabsf(xi[e]) <= FLT_MAX);
             cq[row + k] = 0.0f;
             cu[row + k] = 0.0f;
         }
@@ -103,21 +114,20 @@ __global__ __launch_bounds__(64 * kWaves) void rmclean_kernel(
     }
 
     uint64_t has = 0;  // bit e: element 64 e + lane holds a component
+    const int last = 2 * N - 2;
     int it = 0;
     for (; it < max_iter; ++it) {
         float best = -1.0f, br = 0.0f, bi = 0.0f;
         int bk = 0x7fffffff;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            if (64 * e + lane < N) {
-                const float a2 = __builtin_fmaf(xr[e], xr[e], xi[e] * xi[e]);
-                if (a2 > best) {
-                    best = a2;
-                    bk = 64 * e + lane;
-                    br = xr[e];
-                    bi = xi[e];
-                }
-            }
+            const int k = 64 * e + lane;
+            const float a2 = k < N ? __builtin_fmaf(xr[e], xr[e], xi[e] * xi[e]) : -1.0f;
+            const bool gt = a2 > best;
+            best = gt ? a2 : best;
+            bk = gt ? k : bk;
+            br = gt ? xr[e] : br;
+            bi = gt ? xi[e] : bi;
         }
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
@@ -125,12 +135,11 @@ __global__ __launch_bounds__(64 * kWaves) void rmclean_kernel(
             const int ok = __shfl_xor(bk, off, 64);
             const float orr = __shfl_xor(br, off, 64);
             const float oi = __shfl_xor(bi, off, 64);
-            if (ob > best || (ob == best && ok < bk)) {
-                best = ob;
-                bk = ok;
-                br = orr;
-                bi = oi;
-            }
+            const bool take = ob > best || (ob == best && ok < bk);
+            best = take ? ob : best;
+            bk = take ? ok : bk;
+            br = take ? orr : br;
+            bi = take ? oi : bi;
         }
         if (sqrtf(best) < cutoff) break;
         const float cr = gain * br, ci = gain * bi;
@@ -142,12 +151,10 @@ __global__ __launch_bounds__(64 * kWaves) void rmclean_kernel(
         const int base = N - 1 - bk;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            const int k = 64 * e + lane;
-            if (k < N) {
-                const float2 R = R2[base + k];
-                xr[e] = __builtin_fmaf(-cr, R.x, __builtin_fmaf(ci, R.y, xr[e]));
-                xi[e] = __builtin_fmaf(-cr, R.y, __builtin_fmaf(-ci, R.x, xi[e]));
-            }
+            const int t = base + 64 * e + lane;
+            const float2 R = R2[t < last ? t : last];
+            xr[e] = __builtin_fmaf(-cr, R.x, __builtin_fmaf(ci, R.y, xr[e]));
+            xi[e] = __builtin_fmaf(-cr, R.y, __builtin_fmaf(-ci, R.x, xi[e]));
         }
     }
     if (niter && lane == 0) niter[l] = it;
@@ -161,8 +168,9 @@ __global__ __launch_bounds__(64 * kWaves) void rmclean_kernel(
     }
     if (!restore) return;
     // restored = residual + components convolved with G, component by
-    // component in (e, lane) order.
-#pragma unroll
+    // component in (e, lane) order (the outer loop is kept rolled: only the
+    // inner one indexes the register arrays).
+#pragma unroll 1
     for (int e = 0; e < E; ++e) {
         uint64_t m = __ballot((has >> e) & 1);
         float vr = 0.0f, vi = 0.0f;
@@ -178,12 +186,10 @@ __global__ __launch_bounds__(64 * kWaves) void rmclean_kernel(
             const int base = N - 1 - kc;
 #pragma unroll
             for (int e2 = 0; e2 < E; ++e2) {
-                const int k = 64 * e2 + lane;
-                if (k < N) {
-                    const float g = G[base + k];
-                    xr[e2] = __builtin_fmaf(c_r, g, xr[e2]);
-                    xi[e2] = __builtin_fmaf(c_i, g, xi[e2]);
-                }
+                const int t = base + 64 * e2 + lane;
+                const float g = G[t < last ? t : last];
+                xr[e2] = __builtin_fmaf(c_r, g, xr[e2]);
+                xi[e2] = __builtin_fmaf(c_i, g, xi[e2]);
             }
         }
     }
@@ -202,12 +208,13 @@ hipError_t launch_e(const float* Fq, const float* Fu, int64_t nlos, int N, const
                     const float* G, float gain, float cutoff, int max_iter, float* rq, float* ru,
                     float* cq, float* cu, float* Rq, float* Ru, int32_t* niter, hipStream_t s)
 {
+    constexpr int W = waves_of<E>();
     const size_t lds = (size_t)(2 * N - 1) * sizeof(float2);
     for (int64_t l0 = 0; l0 < nlos;) {
-        const int64_t n = std::min<int64_t>(nlos - l0, max_items(kWaves, 64 * kWaves));
+        const int64_t n = std::min<int64_t>(nlos - l0, max_items(W, 64 * W));
         const int64_t off = l0 * N;
-        hipLaunchKernelGGL(rmclean_kernel<E>, dim3((unsigned)((n + kWaves - 1) / kWaves)),
-                           dim3(64 * kWaves), lds, s, Fq + off, Fu + off, n, N, R2, G, gain, cutoff,
+        hipLaunchKernelGGL(rmclean_kernel<E>, dim3((unsigned)((n + W - 1) / W)),
+                           dim3(64 * W), lds, s, Fq + off, Fu + off, n, N, R2, G, gain, cutoff,
                            max_iter, rq + off, ru + off, cq + off, cu + off, Rq ? Rq + off : nullptr,
                            Ru ? Ru + off : nullptr, niter ? niter + l0 : nullptr);
         if (hipError_t e = hipGetLastError()) return e;

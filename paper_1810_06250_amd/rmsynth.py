@@ -59,6 +59,7 @@ SIGNATURES = {
     "rmsynth_peak_fit": (ctypes.c_int, [_P, _P, _P, _P, _I64, _P, _P, _P]),
     "rmsynth_adjoint": (ctypes.c_int, [_P, _P, _P, _I64, _I32, _P, _P, _P, _SZ, _P]),
     "rmsynth_adjoint_workspace_size": (ctypes.c_int, [_P, _I64, _I32, ctypes.POINTER(_SZ)]),
+    "rmsynth_execute_nufft": (ctypes.c_int, [_P, _P, _P, _I64, _P, _P, _P, _P]),
     "rmsynth_rmclean": (ctypes.c_int, [_P, _P, _P, _I64, ctypes.c_float, ctypes.c_float, _I32, _D,
                                        _P, _P, _P, _P, _P, _P, _P, _P, _SZ, _P]),
     "rmsynth_rmclean_workspace_size": (ctypes.c_int, [_P, ctypes.POINTER(_SZ)]),
@@ -380,6 +381,18 @@ def rmsynth_adjoint(plan, Cq, Cu, nlos: int, precision: int, Pq, Pu, workspace=N
         int(workspace_bytes), _stream(stream)))
 
 
+def rmsynth_execute_nufft(plan, Q, U, nlos: int, Fq, Fu, Fabs=None, stream=None):
+    import torch
+    nchan, nphi = _plan_dims(plan)
+    _need_cube(Q, U, int(nlos), nchan, RMSYNTH_LOS_MAJOR)
+    for t, name in ((Fq, "Fq"), (Fu, "Fu"), (Fabs, "Fabs")):
+        _need_rows(t, name, int(nlos), nphi)
+    f32 = torch.float32
+    _check("rmsynth_execute_nufft", load_library().rmsynth_execute_nufft(
+        plan, _dev(Q, "Q", f32), _dev(U, "U", f32), int(nlos), _dev(Fq, "Fq", f32),
+        _dev(Fu, "Fu", f32), _dev(Fabs, "Fabs", f32), _stream(stream)))
+
+
 def rmsynth_rmclean_workspace_size(plan) -> int:
     b = ctypes.c_size_t()
     _check("rmsynth_rmclean_workspace_size", load_library().rmsynth_rmclean_workspace_size(
@@ -667,6 +680,16 @@ class Plan:
         ws = torch.empty(nb, dtype=torch.uint8, device=Cq.device) if nb else None
         rmsynth_adjoint(self.handle, Cq, Cu, nlos, precision, Pq, Pu, ws, nb)
         return Pq, Pu
+
+    def execute_nufft(self, Q, U, want_abs: bool = False):
+        """F by the non-uniform FFT (rmsynth_execute_nufft), LOS-major input."""
+        import torch
+        nlos = Q.shape[0]
+        Fq = torch.empty((nlos, self.nphi), dtype=torch.float32, device=Q.device)
+        Fu = torch.empty_like(Fq)
+        Fa = torch.empty_like(Fq) if want_abs else None
+        rmsynth_execute_nufft(self.handle, Q, U, nlos, Fq, Fu, Fa)
+        return Fq, Fu, Fa
 
     def rmclean(self, Fq, Fu, gain: float, cutoff: float, max_iter: int,
                 fwhm: float = float("nan"), restore: bool = True):
