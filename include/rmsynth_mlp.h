@@ -134,6 +134,24 @@ int rmsynth_gate_execute(rmsynth_plan_t plan, rmsynth_mlp_t mlp, const float* Q,
                          int32_t* gated, void* workspace, size_t workspace_bytes, void* stream);
 
 /*
+ * rmsynth_gate_search -- rmsynth_gate_execute with the gated lines of sight
+ * searched by rmsynth_search in the given precision (F never stored): gated
+ * outputs are bit for bit those of rmsynth_search over the whole cube in that
+ * precision, the others as rmsynth_gate_execute.  workspace: at least
+ * rmsynth_gate_search_workspace_size() bytes.  Errors as rmsynth_gate_execute,
+ * plus EINVAL / EUNSUPPORTED for the precision as rmsynth_search.
+ */
+int rmsynth_gate_search(rmsynth_plan_t plan, rmsynth_mlp_t mlp, const float* Q, const float* U,
+                        int64_t nlos, int32_t precision, float tau, int32_t* idx, float* phi_pk,
+                        float* amp, int32_t* gated, void* workspace, size_t workspace_bytes,
+                        void* stream);
+
+/* rmsynth_gate_search_workspace_size -- device workspace rmsynth_gate_search
+ * needs for `nlos` lines of sight in this precision. */
+int rmsynth_gate_search_workspace_size(rmsynth_plan_t plan, rmsynth_mlp_t mlp, int64_t nlos,
+                                       int32_t precision, size_t* bytes);
+
+/*
  * Training data.  Synthetic spectra of the sky model of Section 2.1: a
  * Faraday-thin screen P0 exp(2i(chi0 + phi0 lambda^2)) (eqs. (1), (3)), two
  * such screens, or a Burn slab of width W, P0 exp(2i(chi0 + phic lambda^2))

@@ -45,8 +45,8 @@ void free_plan(rmsynth_plan_s* p)
     if (!p) return;
     free_plan(p->adj);
     void* bufs[] = {p->d_b, p->d_lambda2, p->d_w, p->d_phi, p->d_base, p->d_Tbf[0], p->d_Tbf[1],
-                    p->d_Thf[0], p->d_Thf[1], p->d_nufft_rot, p->d_nufft_off, p->d_nufft_ej,
-                    p->d_nufft_ew, p->d_nufft_tw, p->d_nufft_deconv};
+                    p->d_Thf[0], p->d_Thf[1], p->d_nufft_rot, p->d_nufft_off, p->d_nufft_ent,
+                    p->d_nufft_tw, p->d_nufft_deconv};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     delete p;

@@ -49,11 +49,10 @@ struct rmsynth_plan_s {
     rmsynth_plan_s* adj;
     // NUFFT evaluation (uniform grids with nufft_n <= kNufftMaxGrid; nufft_n
     // = 0 otherwise): tables of nufft_plan.cpp.
-    int32_t nufft_n, nufft_kc;
+    int32_t nufft_n, nufft_kc, nufft_nocc;
     float2* d_nufft_rot;    // [nchan]
-    int* d_nufft_off;       // [n + 1]
-    int* d_nufft_ej;        // [entries] channel
-    float* d_nufft_ew;      // [entries] kernel weight
+    int* d_nufft_off;       // [nocc + 1] first entry of each occupied grid point
+    int2* d_nufft_ent;      // [entries] ((channel << 13) | grid point, weight bits)
     float2* d_nufft_tw;     // [n]
     float* d_nufft_deconv;  // [nphi]
 };

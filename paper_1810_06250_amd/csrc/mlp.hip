@@ -627,6 +627,197 @@ __global__ __launch_bounds__(256, 3) void infer_fused_kernel(
     }
 }
 
+// One-pass inference for nchan = 2 PER (PER a multiple of 16), hidden widths
+// 256/256, 16-byte aligned rows.  One workgroup per 64 LOS, two per CU.  The
+// four threads of a row each load one contiguous quarter of [Q | U] (PER
+// floats, all loads in flight at once), so the block is read from HBM once;
+// the row's sum of squares follows from two shuffles, and the normalised
+// halves go to an LDS tile holding the whole 64 x 2 nchan input.  Layer 1
+// then runs over all K-chunks with no barrier and no further input loads
+// (only the weight fragments, two chunks ahead); h1 reuses the tile's LDS;
+// layer 2 and the head are those of infer_fused_kernel.  Rounding points
+// and outputs per LOS do not depend on the LOS's position in the batch.
+template <int PER, bool UNITW>
+__global__ __launch_bounds__(256, 2) void infer_onepass_kernel(
+    const float* __restrict__ Q, const float* __restrict__ U, int64_t nlos,
+    const float* __restrict__ w, const uint4* __restrict__ W1f, const float* __restrict__ b1,
+    const uint4* __restrict__ W2f, const float* __restrict__ b2, const _Float16* __restrict__ W3,
+    const float* __restrict__ b3, float phi_scale, float* __restrict__ phi_hat,
+    float* __restrict__ score)
+{
+    constexpr int nchan = 2 * PER, nin = 4 * PER;
+    constexpr int XS = nin + 8;                       // row stride (halves): odd in 16-byte units
+    constexpr int XB = FR * XS * 2, HB = FR * FHS * 2;
+    constexpr int TB = XB > HB ? XB : HB;
+    __shared__ __align__(16) unsigned char smem[TB + 4 * FR * 2 * 4];
+    _Float16 (*sx)[XS] = reinterpret_cast<_Float16 (*)[XS]>(smem);
+    _Float16 (*sh)[FHS] = reinterpret_cast<_Float16 (*)[FHS]>(smem);
+    float (*part)[FR][2] = reinterpret_cast<float (*)[FR][2]>(smem + TB);
+    const int t = threadIdx.x, lane = t & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int64_t r0 = (int64_t)blockIdx.x * FR;
+    const int lrow = t >> 2, qq = t & 3;
+    // Rows past the end read the last LOS (in bounds); their outputs are never stored.
+    const int64_t ll = r0 + lrow < nlos ? r0 + lrow : nlos - 1;
+    {
+        const float* src = (qq < 2 ? Q : U) + ll * nchan + (qq & 1) * PER;
+        const float* wq = w + (qq & 1) * PER;
+        float v[PER];
+#pragma unroll
+        for (int i = 0; i < PER / 4; ++i) {
+            const float4 a = reinterpret_cast<const float4*>(src)[i];
+            v[4 * i] = a.x; v[4 * i + 1] = a.y; v[4 * i + 2] = a.z; v[4 * i + 3] = a.w;
+        }
+        float ss = 0.0f;
+#pragma unroll
+        for (int i = 0; i < PER / 4; ++i) {
+            const float4 wv = UNITW ? make_float4(1.0f, 1.0f, 1.0f, 1.0f)
+                                    : reinterpret_cast<const float4*>(wq)[i];
+            const float ww[4] = {wv.x, wv.y, wv.z, wv.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float a = ww[e] == 0.0f ? 0.0f : ww[e] * v[4 * i + e];
+                v[4 * i + e] = a;
+                ss = __builtin_fmaf(a, a, ss);
+            }
+        }
+        ss += __shfl_xor(ss, 1, 64);
+        ss += __shfl_xor(ss, 2, 64);
+        const float inv = ss > 0.0f ? 1.0f / sqrtf(ss / (float)nin) : (ss == 0.0f ? 0.0f : ss);
+#pragma unroll
+        for (int i = 0; i < PER / 8; ++i) {
+            f16x8_t xv;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) xv[e] = half_of(v[8 * i + e] * inv);
+            *reinterpret_cast<f16x8_t*>(&sx[lrow][qq * PER + 8 * i]) = xv;
+        }
+    }
+    __syncthreads();
+
+    const int r = lane & 31, hsel = lane >> 5;
+    const int ncol = 64 * wave;
+    f32x16_t acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
+    auto wfrag = [&](const uint4* Wf, int ks, int k0, uint4 (&bv)[2][2]) {
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+            for (int sl = 0; sl < 2; ++sl)
+                bv[cb][sl] = Wf[((int64_t)(2 * wave + cb) * ks + (k0 >> 4) + sl) * 64 + lane];
+    };
+    // Contract K-chunk c from the tile row block of `tile` with the weight
+    // fragments in `cur`, after starting the loads of chunk c + 2 into `nxt`
+    // (the set chunk c - 1 used).  Three register sets rotate, so a fragment
+    // load is first waited on two chunks after it was issued.
+    auto chunk = [&](const _Float16* tile, int ld, const uint4* Wf, int ks, int nch, int c,
+                     uint4 (&cur)[2][2], uint4 (&nxt)[2][2]) {
+        if (c + 2 < nch) wfrag(Wf, ks, (c + 2) * GK, nxt);
+#pragma unroll
+        for (int sl = 0; sl < 2; ++sl) {
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb) {
+                const uint4 a = *reinterpret_cast<const uint4*>(tile + (32 * rb + r) * ld + c * GK + 16 * sl + 8 * hsel);
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb)
+                    acc[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                        __builtin_bit_cast(f16x8_t, a), __builtin_bit_cast(f16x8_t, cur[cb][sl]),
+                        acc[rb][cb], 0, 0, 0);
+            }
+        }
+    };
+    auto layer = [&](const _Float16* tile, int ld, const uint4* Wf, int ks, int nch,
+                     uint4 (&B0)[2][2], uint4 (&B1)[2][2], uint4 (&B2)[2][2]) {
+        int c = 0;
+        for (; c + 2 < nch; c += 3) {
+            chunk(tile, ld, Wf, ks, nch, c, B0, B2);
+            chunk(tile, ld, Wf, ks, nch, c + 1, B1, B0);
+            chunk(tile, ld, Wf, ks, nch, c + 2, B2, B1);
+        }
+        if (c < nch) chunk(tile, ld, Wf, ks, nch, c, B0, B2);
+        if (c + 1 < nch) chunk(tile, ld, Wf, ks, nch, c + 1, B1, B0);
+    };
+    // Layer 1 over the whole input tile.
+    {
+        constexpr int nch = nin / GK, ks1 = nin / 16;
+        uint4 B0[2][2], B1[2][2], B2[2][2];
+        wfrag(W1f, ks1, 0, B0);
+        wfrag(W1f, ks1, GK, B1);
+        layer(&sx[0][0], XS, W1f, ks1, nch, B0, B1, B2);
+    }
+    constexpr int ks2 = FH / 16, nch2 = FH / GK;
+    uint4 w2a[2][2], w2b[2][2];
+    wfrag(W2f, ks2, 0, w2a);
+    wfrag(W2f, ks2, GK, w2b);
+    __syncthreads();  // every wave is done with the input tile: h1 takes its LDS
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+        const int n = ncol + 32 * cb + r;
+        const float bn = b1[n];
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int m = 32 * rb + 8 * (v >> 2) + 4 * hsel + (v & 3);
+                const float z = __builtin_fmaf(1.0f, acc[rb][cb][v], bn);
+                sh[m][n] = half_of(z < 0.0f ? 0.0f : z);
+                acc[rb][cb][v] = 0.0f;
+            }
+    }
+    __syncthreads();
+    {
+        uint4 B2[2][2];
+        layer(&sh[0][0], FHS, W2f, ks2, nch2, w2a, w2b, B2);
+    }
+    float p0[2][16], p1[2][16];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) p0[rb][v] = p1[rb][v] = 0.0f;
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+        const int n = ncol + 32 * cb + r;
+        const float bn = b2[n], w0 = (float)W3[n], w1 = (float)W3[FH + n];
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const float z = __builtin_fmaf(1.0f, acc[rb][cb][v], bn);
+                const float h = (float)half_of(z < 0.0f ? 0.0f : z);
+                p0[rb][v] = __builtin_fmaf(h, w0, p0[rb][v]);
+                p1[rb][v] = __builtin_fmaf(h, w1, p1[rb][v]);
+            }
+    }
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            float a = p0[rb][v], b = p1[rb][v];
+#pragma unroll
+            for (int off = 16; off > 0; off >>= 1) {
+                a += __shfl_xor(a, off, 64);
+                b += __shfl_xor(b, off, 64);
+            }
+            if (r == 0) {
+                const int m = 32 * rb + 8 * (v >> 2) + 4 * hsel + (v & 3);
+                part[wave][m][0] = a;
+                part[wave][m][1] = b;
+            }
+        }
+    __syncthreads();
+    if (t < FR && r0 + t < nlos) {
+        const float o0 = ((part[0][t][0] + part[1][t][0]) + (part[2][t][0] + part[3][t][0])) + b3[0];
+        const float o1 = ((part[0][t][1] + part[1][t][1]) + (part[2][t][1] + part[3][t][1])) + b3[1];
+        phi_hat[r0 + t] = o0 * phi_scale;
+        const float e = expf(-fabsf(o1));
+        score[r0 + t] = o1 >= 0.0f ? 1.0f / (1.0f + e) : e / (1.0f + e);
+    }
+}
+
 unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
 }  // namespace
@@ -779,7 +970,19 @@ hipError_t mlp_launch_infer_fused(const float* Q, const float* U, int64_t nlos, 
         const int64_t blocks = (n + FR - 1) / FR;
         const float* q = Q + l0 * nchan;
         const float* u = U + l0 * nchan;
-        if (vec) {
+#define RMS_ONEPASS(P)                                                                                  \
+    do {                                                                                                \
+        if (unit_w)                                                                                     \
+            hipLaunchKernelGGL((infer_onepass_kernel<P, true>), dim3((unsigned)blocks), dim3(256), 0, s, q, \
+                               u, n, w, W1, b1, W2, b2, W3, b3, phi_scale, phi_hat + l0, score + l0);   \
+        else                                                                                            \
+            hipLaunchKernelGGL((infer_onepass_kernel<P, false>), dim3((unsigned)blocks), dim3(256), 0, s, \
+                               q, u, n, w, W1, b1, W2, b2, W3, b3, phi_scale, phi_hat + l0, score + l0); \
+    } while (0)
+        if (vec && nchan == 288) RMS_ONEPASS(144);
+        else if (vec && nchan == 256) RMS_ONEPASS(128);
+        else if (vec && nchan == 128) RMS_ONEPASS(64);
+        else if (vec) {
             if (unit_w)
                 hipLaunchKernelGGL((infer_fused_kernel<true, true>), dim3((unsigned)blocks), dim3(256), 0, s,
                                    q, u, n, nchan, w, nin_pad, W1, b1, W2, b2, W3, b3, phi_scale,
@@ -793,6 +996,7 @@ hipError_t mlp_launch_infer_fused(const float* Q, const float* U, int64_t nlos, 
                                q, u, n, nchan, w, nin_pad, W1, b1, W2, b2, W3, b3, phi_scale,
                                phi_hat + l0, score + l0);
         }
+#undef RMS_ONEPASS
         if (hipError_t e = hipGetLastError()) return e;
     }
     return hipSuccess;

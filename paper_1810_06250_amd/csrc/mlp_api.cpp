@@ -478,7 +478,11 @@ struct GateLayout {
     size_t score, counts, list, gQ, gU, Fq, Fu, gidx, gphi, gamp, total;
 };
 
-static GateLayout gate_layout(const rmsynth_plan_s* p, int64_t nlos)
+// With search = true the gated LOS go through the peaks-only search
+// (rmsynth_search) in the given precision: its workspace takes the place of
+// the F buffers.
+static GateLayout gate_layout(const rmsynth_plan_s* p, int64_t nlos, bool search = false,
+                              int32_t precision = RMSYNTH_FP32)
 {
     GateLayout L{};
     L.G = std::max<int64_t>(1, std::min(nlos, kGateChunk));
@@ -494,8 +498,13 @@ static GateLayout gate_layout(const rmsynth_plan_s* p, int64_t nlos)
     L.list = take(8 * n);
     L.gQ = take(4 * (size_t)L.G * p->nchan);
     L.gU = take(4 * (size_t)L.G * p->nchan);
-    L.Fq = take(4 * (size_t)L.G * p->nphi);
-    L.Fu = take(4 * (size_t)L.G * p->nphi);
+    if (search) {
+        L.Fq = take(search_workspace_bytes(p, L.G, precision));
+        L.Fu = L.Fq;
+    } else {
+        L.Fq = take(4 * (size_t)L.G * p->nphi);
+        L.Fu = take(4 * (size_t)L.G * p->nphi);
+    }
     L.gidx = take(4 * (size_t)L.G);
     L.gphi = take(4 * (size_t)L.G);
     L.gamp = take(4 * (size_t)L.G);
@@ -512,21 +521,24 @@ int rmsynth_gate_workspace_size(rmsynth_plan_t p, rmsynth_mlp_t m, int64_t nlos,
     return rms_ok();
 }
 
-int rmsynth_gate_execute(rmsynth_plan_t p, rmsynth_mlp_t m, const float* Q, const float* U,
-                         int64_t nlos, float tau, int32_t* idx, float* phi_pk, float* amp,
-                         int32_t* gated, void* workspace, size_t workspace_bytes, void* stream)
+static int gate_run(rmsynth_plan_t p, rmsynth_mlp_t m, const float* Q, const float* U, int64_t nlos,
+                    bool search, int32_t precision, float tau, int32_t* idx, float* phi_pk, float* amp,
+                    int32_t* gated, void* workspace, size_t workspace_bytes, void* stream, const char* who)
 {
-    const char* who = "rmsynth_gate_execute";
     if (!p || !m) return rms_fail(RMSYNTH_EINVAL, "%s: plan or network is NULL", who);
     if (p->nchan != m->nchan)
         return rms_fail(RMSYNTH_EINVAL, "%s: plan has %d channels, network %d", who, p->nchan, m->nchan);
     if (nlos < 0 || nlos > 0x7fffffffLL)
         return rms_fail(RMSYNTH_EINVAL, "%s: nlos=%lld", who, (long long)nlos);
     if (std::isnan(tau)) return rms_fail(RMSYNTH_EINVAL, "%s: tau is NaN", who);
+    if (precision < RMSYNTH_FP32 || precision > RMSYNTH_SPLIT_FP16)
+        return rms_fail(RMSYNTH_EINVAL, "%s: precision=%d", who, precision);
+    if (precision == RMSYNTH_SPLIT_FP16 && !p->uniform)
+        return rms_fail(RMSYNTH_EUNSUPPORTED, "%s: the FP16 split needs a uniform phi grid", who);
     if (nlos == 0) return rms_ok();
     if (!Q || !U || !idx || !phi_pk || !amp || !gated)
         return rms_fail(RMSYNTH_EINVAL, "%s: NULL buffer", who);
-    const GateLayout L = gate_layout(p, nlos);
+    const GateLayout L = gate_layout(p, nlos, search, precision);
     if (!workspace || workspace_bytes < L.total)
         return rms_fail(RMSYNTH_EWORKSPACE, "%s: needs %zu workspace bytes, got %zu", who, L.total,
                         workspace ? workspace_bytes : (size_t)0);
@@ -557,14 +569,49 @@ int rmsynth_gate_execute(rmsynth_plan_t p, rmsynth_mlp_t m, const float* Q, cons
         const int64_t n = std::min<int64_t>(L.G, ngated - r0);
         if ((e = gate_launch_gather(Q, U, list + r0, n, p->nchan, gQ, gU, s)) != hipSuccess)
             return rms_hip_fail(e, who);
-        if (int rc = rmsynth_execute(p, gQ, gU, n, RMSYNTH_LOS_MAJOR, RMSYNTH_FP32, Fq, Fu, nullptr,
-                                     nullptr, 0, stream))
-            return rc;
-        if (int rc = rmsynth_peaks(p, Fq, Fu, n, gidx, gphi, gamp, nullptr, nullptr, stream)) return rc;
+        if (search) {
+            if (int rc = search_impl(p, gQ, gU, n, RMSYNTH_LOS_MAJOR, precision, gidx, gphi, gamp, nullptr,
+                                     nullptr, nullptr, nullptr, Fq, search_workspace_bytes(p, L.G, precision),
+                                     stream, who))
+                return rc;
+        } else {
+            if (int rc = rmsynth_execute(p, gQ, gU, n, RMSYNTH_LOS_MAJOR, RMSYNTH_FP32, Fq, Fu, nullptr,
+                                         nullptr, 0, stream))
+                return rc;
+            if (int rc = rmsynth_peaks(p, Fq, Fu, n, gidx, gphi, gamp, nullptr, nullptr, stream)) return rc;
+        }
         if ((e = gate_launch_scatter(list + r0, n, gidx, gphi, gamp, idx, phi_pk, amp, s)) != hipSuccess)
             return rms_hip_fail(e, who);
     }
     return rms_ok();
+}
+
+int rmsynth_gate_execute(rmsynth_plan_t p, rmsynth_mlp_t m, const float* Q, const float* U,
+                         int64_t nlos, float tau, int32_t* idx, float* phi_pk, float* amp,
+                         int32_t* gated, void* workspace, size_t workspace_bytes, void* stream)
+{
+    return gate_run(p, m, Q, U, nlos, false, RMSYNTH_FP32, tau, idx, phi_pk, amp, gated, workspace,
+                    workspace_bytes, stream, "rmsynth_gate_execute");
+}
+
+int rmsynth_gate_search_workspace_size(rmsynth_plan_t p, rmsynth_mlp_t m, int64_t nlos,
+                                       int32_t precision, size_t* bytes)
+{
+    if (!p || !m || !bytes) return rms_fail(RMSYNTH_EINVAL, "rmsynth_gate_search_workspace_size: NULL argument");
+    if (nlos < 0 || nlos > 0x7fffffffLL)
+        return rms_fail(RMSYNTH_EINVAL, "rmsynth_gate_search_workspace_size: nlos=%lld", (long long)nlos);
+    if (precision < RMSYNTH_FP32 || precision > RMSYNTH_SPLIT_FP16)
+        return rms_fail(RMSYNTH_EINVAL, "rmsynth_gate_search_workspace_size: precision=%d", precision);
+    *bytes = gate_layout(p, nlos, true, precision).total;
+    return rms_ok();
+}
+
+int rmsynth_gate_search(rmsynth_plan_t p, rmsynth_mlp_t m, const float* Q, const float* U, int64_t nlos,
+                        int32_t precision, float tau, int32_t* idx, float* phi_pk, float* amp,
+                        int32_t* gated, void* workspace, size_t workspace_bytes, void* stream)
+{
+    return gate_run(p, m, Q, U, nlos, true, precision, tau, idx, phi_pk, amp, gated, workspace,
+                    workspace_bytes, stream, "rmsynth_gate_search");
 }
 
 // Labelling workspace: Fq, Fu [C][nphi] | idx, phi, amp [C], C = min(nlos, kGateChunk).

@@ -3,10 +3,12 @@
 //   n        grid size: the smallest power of two >= max(2 nphi, 16);
 //   kc       index of the grid's centre phi_c = phi_0 + kc dphi, kc = nphi / 2;
 //   rot_j    K w_j exp(-2i a_j phi_c) (the factor c_j = rot_j P_j);
-//   CSR      for every grid point p, the channels j (w_j > 0) whose kernel
-//            reaches it, periodic distance d = x_p - x_j wrapped to [-pi, pi),
-//            |d| < alpha, with weight psi(d); x_p = 2 pi p / n,
-//            x_j = 2 a_j dphi mod 2 pi;
+//   entries  for every grid point p in order, the channels j (w_j > 0) whose
+//            kernel reaches it, periodic distance d = x_p - x_j wrapped to
+//            [-pi, pi), |d| < alpha, with weight psi(d); x_p = 2 pi p / n,
+//            x_j = 2 a_j dphi mod 2 pi; packed ((j << 13) | p, bits of
+//            psi(d)); only grid points with entries are listed, off[i] the
+//            first entry of the i-th of them;
 //   tw_t     exp(-2 pi i t / n);
 //   deconv_k (2 pi / n) / psi_hat(k - kc), psi_hat by 512-point Gauss-Legendre
 //            quadrature of int psi(t) cos(m t) dt over [-alpha, alpha];
@@ -16,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstring>
 #include <vector>
 
 #include "common.h"
@@ -92,16 +95,20 @@ int build_nufft_tables(rmsynth_plan_s* p, const double* lambda2, const double* w
             if (std::fabs(d) < alpha) lists[pp].push_back({j, (float)psi(d)});
         }
     }
-    std::vector<int> off(n + 1, 0), ej;
-    std::vector<float> ew;
+    std::vector<int> off;
+    std::vector<int2> ent;
     for (int pp = 0; pp < n; ++pp) {
-        off[pp] = (int)ej.size();
+        if (lists[pp].empty()) continue;
+        off.push_back((int)ent.size());
         for (auto& e : lists[pp]) {
-            ej.push_back(e.first);
-            ew.push_back(e.second);
+            float wt = e.second;
+            int bits;
+            std::memcpy(&bits, &wt, sizeof bits);
+            ent.push_back(make_int2((e.first << 13) | pp, bits));
         }
     }
-    off[n] = (int)ej.size();
+    const int nocc = (int)off.size();
+    off.push_back((int)ent.size());
     std::vector<float2> tw(n);
     for (int t = 0; t < n; ++t)
         tw[t] = make_float2((float)std::cos(2.0 * M_PI * t / n), (float)(-std::sin(2.0 * M_PI * t / n)));
@@ -117,11 +124,11 @@ int build_nufft_tables(rmsynth_plan_s* p, const double* lambda2, const double* w
     }
     if (int rc = upload(&p->d_nufft_rot, rot)) return rc;
     if (int rc = upload(&p->d_nufft_off, off)) return rc;
-    if (int rc = upload(&p->d_nufft_ej, ej)) return rc;
-    if (int rc = upload(&p->d_nufft_ew, ew)) return rc;
+    if (int rc = upload(&p->d_nufft_ent, ent)) return rc;
     if (int rc = upload(&p->d_nufft_tw, tw)) return rc;
     if (int rc = upload(&p->d_nufft_deconv, deconv)) return rc;
     p->nufft_n = n;
     p->nufft_kc = kc;
+    p->nufft_nocc = nocc;
     return RMSYNTH_OK;
 }

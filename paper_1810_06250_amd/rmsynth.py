@@ -80,6 +80,9 @@ SIGNATURES = {
     "rmsynth_gate_workspace_size": (ctypes.c_int, [_P, _P, _I64, ctypes.POINTER(_SZ)]),
     "rmsynth_gate_execute": (ctypes.c_int, [_P, _P, _P, _P, _I64, ctypes.c_float, _P, _P, _P, _P,
                                             _P, _SZ, _P]),
+    "rmsynth_gate_search": (ctypes.c_int, [_P, _P, _P, _P, _I64, _I32, ctypes.c_float, _P, _P, _P, _P,
+                                           _P, _SZ, _P]),
+    "rmsynth_gate_search_workspace_size": (ctypes.c_int, [_P, _P, _I64, _I32, ctypes.POINTER(_SZ)]),
     "rmsynth_train_workspace_size": (ctypes.c_int, [_P, _I64, ctypes.POINTER(_SZ)]),
     "rmsynth_synth_training": (ctypes.c_int, [_P, _P, ctypes.c_uint64, _I64, _I64, _P, _P, _P, _P,
                                               _P, _P, _P, _SZ, _P]),
@@ -539,6 +542,29 @@ def rmsynth_gate_execute(plan, mlp, Q, U, nlos: int, tau: float, idx, phi_pk, am
         _stream(stream)))
 
 
+def rmsynth_gate_search_workspace_size(plan, mlp, nlos: int, precision: int) -> int:
+    b = ctypes.c_size_t()
+    _check("rmsynth_gate_search_workspace_size", load_library().rmsynth_gate_search_workspace_size(
+        plan, mlp, int(nlos), int(precision), ctypes.byref(b)))
+    return b.value
+
+
+def rmsynth_gate_search(plan, mlp, Q, U, nlos: int, precision: int, tau: float, idx, phi_pk, amp,
+                        gated, workspace, workspace_bytes: int, stream=None):
+    import torch
+    nchan, _ = _plan_dims(plan)
+    _need_cube(Q, U, int(nlos), nchan, RMSYNTH_LOS_MAJOR)
+    for t, name in ((idx, "idx"), (phi_pk, "phi_pk"), (amp, "amp"), (gated, "gated")):
+        _need(t, name, int(nlos))
+    _need_bytes(workspace, int(workspace_bytes))
+    f32, i32 = torch.float32, torch.int32
+    _check("rmsynth_gate_search", load_library().rmsynth_gate_search(
+        plan, mlp, _dev(Q, "Q", f32), _dev(U, "U", f32), int(nlos), int(precision), float(tau),
+        _dev(idx, "idx", i32), _dev(phi_pk, "phi_pk", f32), _dev(amp, "amp", f32),
+        _dev(gated, "gated", i32), _dev(workspace, "workspace"), int(workspace_bytes),
+        _stream(stream)))
+
+
 class TrainSpec(ctypes.Structure):
     """rmsynth_train_spec: class mix, parameter ranges, noise and detection threshold."""
     _fields_ = [(n, ctypes.c_double) for n in (
@@ -810,7 +836,10 @@ class Mlp:
         rmsynth_mlp_infer(self.handle, Q, U, n, phi_hat, score)
         return phi_hat, score
 
-    def gate(self, plan: "Plan", Q, U, tau: float):
+    def gate(self, plan: "Plan", Q, U, tau: float, precision: Optional[int] = None):
+        """Gated peak search: rmsynth_gate_execute (FP32 transform + peaks on
+        the gated LOS), or with a precision rmsynth_gate_search (the
+        peaks-only search in that precision)."""
         import torch
         n = Q.shape[0]
         dev = Q.device
@@ -818,8 +847,14 @@ class Mlp:
                    phi_pk=torch.empty(n, dtype=torch.float32, device=dev),
                    amp=torch.empty(n, dtype=torch.float32, device=dev),
                    gated=torch.empty(n, dtype=torch.int32, device=dev))
-        nb = rmsynth_gate_workspace_size(plan.handle, self.handle, n)
-        ws = torch.empty(nb, dtype=torch.uint8, device=dev)
-        rmsynth_gate_execute(plan.handle, self.handle, Q, U, n, tau, out["idx"], out["phi_pk"],
-                             out["amp"], out["gated"], ws, nb)
+        if precision is None:
+            nb = rmsynth_gate_workspace_size(plan.handle, self.handle, n)
+            ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+            rmsynth_gate_execute(plan.handle, self.handle, Q, U, n, tau, out["idx"], out["phi_pk"],
+                                 out["amp"], out["gated"], ws, nb)
+        else:
+            nb = rmsynth_gate_search_workspace_size(plan.handle, self.handle, n, precision)
+            ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+            rmsynth_gate_search(plan.handle, self.handle, Q, U, n, precision, tau, out["idx"],
+                                out["phi_pk"], out["amp"], out["gated"], ws, nb)
         return out

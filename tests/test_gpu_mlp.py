@@ -331,6 +331,25 @@ def test_gate_matches_ungated_on_gated_lines(n, tau):
         assert mism == 0 and bad == 0, (mism, bad)
 
 
+@pytest.mark.parametrize("prec", [rs.RMSYNTH_SPLIT_BF16, rs.RMSYNTH_FP32])
+def test_gate_search_matches_the_search_on_gated_lines(prec):
+    """rmsynth_gate_search: the gated LOS get bit for bit what rmsynth_search
+    gives over the whole cube in the same precision; the rest as the FP32 gate."""
+    n = 20_000
+    note(f"gate search n={n} prec={prec}")
+    plan, net, Q, U, lam, w, phi = _gate_setup(n)
+    Qd, Ud = dev32(Q), dev32(U)
+    out = {k: host(v) for k, v in net.gate(plan, Qd, Ud, 0.5, precision=prec).items()}
+    ref = {k: host(v) for k, v in net.gate(plan, Qd, Ud, 0.5).items()}
+    full = {k: host(v) for k, v in plan.search(Qd, Ud, rs.RMSYNTH_LOS_MAJOR, prec).items()}
+    g = out["gated"].astype(bool)
+    np.testing.assert_array_equal(out["gated"], ref["gated"])
+    for k in ("idx", "phi_pk", "amp"):
+        np.testing.assert_array_equal(out[k][g], full[k][g])
+        np.testing.assert_array_equal(out[k][~g], ref[k][~g])
+    assert g.any() and (~g).any()
+
+
 def test_gate_argument_errors():
     plan, net, Q, U, lam, w, phi = _gate_setup(10)
     other = rs.Plan(lam[:-1], w[:-1], phi)
