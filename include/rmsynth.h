@@ -133,11 +133,11 @@ int rmsynth_rmsf(rmsynth_plan_t plan, float* R_re, float* R_im, void* stream);
  *   workspace, workspace_bytes: device scratch of at least
  *            rmsynth_workspace_size() bytes (may be NULL when that is 0).
  * A LOS whose unflagged channels hold a non-finite value gets non-finite
- * outputs; other LOS are unaffected.  RMSYNTH_SPLIT_FP16 needs a uniform phi
- * grid (EUNSUPPORTED otherwise); the workspace is overwritten, and calls that
- * share one workspace must not overlap.
+ * outputs; other LOS are unaffected.  RMSYNTH_SPLIT_FP16 keeps a per-LOS
+ * power-of-two scale in the workspace (any phi grid); the workspace is
+ * overwritten, and calls that share one workspace must not overlap.
  * Errors: EINVAL (NULL buffers with nlos > 0, bad layout/precision, wrong
- * device current), EUNSUPPORTED, EWORKSPACE, EHIP (launch failure).
+ * device current), EWORKSPACE, EHIP (launch failure).
  */
 int rmsynth_execute(rmsynth_plan_t plan, const float* Q, const float* U, int64_t nlos,
                     int32_t layout, int32_t precision,
@@ -233,10 +233,9 @@ size_t rmsynth_search_noalloc_scratch_bytes(void);
  * model Faraday dispersion function, come from here.
  *   Cq, Cu   [nlos][nphi] device float: Re and Im of the components.
  *   Pq, Pu   [nlos][nchan] device float (LOS-major): Re and Im of P.
- *   precision  RMSYNTH_FP32 or RMSYNTH_SPLIT_BF16 (the phase tiles are
- *            generated per element unless the channels are uniform in
- *            lambda^2); RMSYNTH_SPLIT_FP16 only for channels uniform in
- *            lambda^2 (EUNSUPPORTED otherwise).
+ *   precision  any rmsynth_precision (the phase tiles are generated per
+ *            element unless the channels are uniform in lambda^2, then the
+ *            factored tables serve).
  *   workspace  rmsynth_adjoint_workspace_size() bytes (0 except FP16), or
  *            less down to its value for 128 LOS (batches).
  * Every channel gets a value (weights do not enter).  A LOS with a

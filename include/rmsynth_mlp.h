@@ -139,7 +139,7 @@ int rmsynth_gate_execute(rmsynth_plan_t plan, rmsynth_mlp_t mlp, const float* Q,
  * outputs are bit for bit those of rmsynth_search over the whole cube in that
  * precision, the others as rmsynth_gate_execute.  workspace: at least
  * rmsynth_gate_search_workspace_size() bytes.  Errors as rmsynth_gate_execute,
- * plus EINVAL / EUNSUPPORTED for the precision as rmsynth_search.
+ * plus EINVAL for a bad precision.
  */
 int rmsynth_gate_search(rmsynth_plan_t plan, rmsynth_mlp_t mlp, const float* Q, const float* U,
                         int64_t nlos, int32_t precision, float tau, int32_t* idx, float* phi_pk,

@@ -297,8 +297,6 @@ int check_execute_args(const rmsynth_plan_s* p, int64_t nlos, int32_t layout, in
         return rms_fail(RMSYNTH_EINVAL, "%s: layout=%d", who, layout);
     if (precision < RMSYNTH_FP32 || precision > RMSYNTH_SPLIT_FP16)
         return rms_fail(RMSYNTH_EINVAL, "%s: precision=%d", who, precision);
-    if (precision == RMSYNTH_SPLIT_FP16 && !p->uniform)
-        return rms_fail(RMSYNTH_EUNSUPPORTED, "%s: the FP16 split needs a uniform phi grid", who);
     return RMSYNTH_OK;
 }
 
@@ -573,8 +571,6 @@ int rmsynth_adjoint(rmsynth_plan_t p, const float* Cq, const float* Cu, int64_t 
 {
     const char* who = "rmsynth_adjoint";
     if (!p) return rms_fail(RMSYNTH_EINVAL, "%s: plan is NULL", who);
-    if (precision == RMSYNTH_SPLIT_FP16 && !p->adj->uniform)
-        return rms_fail(RMSYNTH_EUNSUPPORTED, "%s: the FP16 split needs channels uniform in lambda^2", who);
     if (int rc = check_execute_args(p->adj, nlos, RMSYNTH_LOS_MAJOR, precision, who)) return rc;
     if (nlos == 0) return rms_ok();
     if (!Cq || !Cu || !Pq || !Pu) return rms_fail(RMSYNTH_EINVAL, "%s: NULL buffer", who);

@@ -533,8 +533,6 @@ static int gate_run(rmsynth_plan_t p, rmsynth_mlp_t m, const float* Q, const flo
     if (std::isnan(tau)) return rms_fail(RMSYNTH_EINVAL, "%s: tau is NaN", who);
     if (precision < RMSYNTH_FP32 || precision > RMSYNTH_SPLIT_FP16)
         return rms_fail(RMSYNTH_EINVAL, "%s: precision=%d", who, precision);
-    if (precision == RMSYNTH_SPLIT_FP16 && !p->uniform)
-        return rms_fail(RMSYNTH_EUNSUPPORTED, "%s: the FP16 split needs a uniform phi grid", who);
     if (nlos == 0) return rms_ok();
     if (!Q || !U || !idx || !phi_pk || !amp || !gated)
         return rms_fail(RMSYNTH_EINVAL, "%s: NULL buffer", who);

@@ -646,6 +646,7 @@ __global__ void factor_tables_kernel(const double* __restrict__ bj, const float*
 }
 
 // Per-LOS power-of-two scale for the FP16 split: M = K max_j w_j max(|Q_j|, |U_j|)
+// (K = 1 for the per-element split kernel, which applies K after the sums)
 // bounds the rotated components up to a factor sqrt 2; the scale 2^(13 - E), with
 // M < 2^E, keeps them below 2^14 (half precision's largest finite value is
 // 65504), so hi and lo stay normal down to 2^-10 of the LOS's largest value.
@@ -736,14 +737,17 @@ hipError_t launch_t(const rmsynth_plan_s& p, const ExecArgs& a)
 
 hipError_t launch_los_scale(const rmsynth_plan_s& p, const ExecArgs& a)
 {
+    // The factored kernels fold K into the data they split; the per-element
+    // split kernel applies it in the epilogue, so its scale ignores K.
+    const float k = p.uniform ? (float)p.K : 1.0f;
     if (a.layout == RMSYNTH_LOS_MAJOR)
         hipLaunchKernelGGL(los_scale_kernel<RMSYNTH_LOS_MAJOR>, dim3((unsigned)((a.nlos + 3) / 4)),
-                           dim3(256), 0, a.stream, a.Q, a.U, a.nlos, a.ld, p.nchan, p.d_w,
-                           (float)p.K, a.los_scale);
+                           dim3(256), 0, a.stream, a.Q, a.U, a.nlos, a.ld, p.nchan, p.d_w, k,
+                           a.los_scale);
     else
         hipLaunchKernelGGL(los_scale_kernel<RMSYNTH_FREQ_MAJOR>, dim3((unsigned)((a.nlos + 255) / 256)),
-                           dim3(256), 0, a.stream, a.Q, a.U, a.nlos, a.ld, p.nchan, p.d_w,
-                           (float)p.K, a.los_scale);
+                           dim3(256), 0, a.stream, a.Q, a.U, a.nlos, a.ld, p.nchan, p.d_w, k,
+                           a.los_scale);
     return hipGetLastError();
 }
 

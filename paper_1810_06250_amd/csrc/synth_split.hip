@@ -52,7 +52,8 @@ __global__ __launch_bounds__(256, 2) void synth_split_kernel(
     const float* __restrict__ Q, const float* __restrict__ U, int64_t nlos, int64_t ld,
     int nchan, int vec4, const double* __restrict__ bj, const float* __restrict__ wj, int nk,
     const double* __restrict__ phik, int nphi, int tiles_n, float K,
-    float* __restrict__ Fq, float* __restrict__ Fu, float* __restrict__ Fabs)
+    float* __restrict__ Fq, float* __restrict__ Fu, float* __restrict__ Fabs,
+    const float* __restrict__ los_scale)
 {
     __shared__ Smem sm;
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -73,6 +74,10 @@ __global__ __launch_bounds__(256, 2) void synth_split_kernel(
     const int la = t >> 1, hA = t & 1;
     const int64_t lg = l0 + la;
     const bool lvalid = lg < nlos;
+    // FP16: per-LOS power-of-two scale keeping both halves of the split in
+    // half precision's normal range (from the weighted data, K not applied);
+    // undone exactly in the epilogue.
+    const float lsc = FP16 && lvalid ? los_scale[lg] : 1.0f;
 
     f32x16_t acc[4][2];
 #pragma unroll
@@ -114,8 +119,12 @@ __global__ __launch_bounds__(256, 2) void synth_split_kernel(
         uint32_t rh[4], rl[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const float x = (w[i] != 0.0f) ? w[i] * q[i] : 0.0f;
-            const float y = (w[i] != 0.0f) ? w[i] * u[i] : 0.0f;
+            float x = (w[i] != 0.0f) ? w[i] * q[i] : 0.0f;
+            float y = (w[i] != 0.0f) ? w[i] * u[i] : 0.0f;
+            if (FP16) {
+                x *= lsc;
+                y *= lsc;
+            }
             split2<FP16>(x, y, rh[i], rl[i]);
         }
         // ---- B operand.
@@ -177,8 +186,14 @@ __global__ __launch_bounds__(256, 2) void synth_split_kernel(
                 const int row = 128 * wr + 32 * rb + 8 * (v >> 2) + 4 * half + (v & 3);
                 const int64_t l = l0 + (row >> 1);
                 if (l < nlos && n < nphi) {
-                    const float fq = K * acc[rb][cb][v];
-                    const float fu = K * acc[rb][cb][v + 1];
+                    float aq = acc[rb][cb][v], au = acc[rb][cb][v + 1];
+                    if (FP16) {  // multiply by 2^-e of the scale 2^e: exact
+                        const float inv = __builtin_ldexpf(1.0f, 1 - __builtin_amdgcn_frexp_expf(los_scale[l]));
+                        aq *= inv;
+                        au *= inv;
+                    }
+                    const float fq = K * aq;
+                    const float fu = K * au;
                     Fq[l * nphi + n] = fq;
                     Fu[l * nphi + n] = fu;
                     if (Fabs) Fabs[l * nphi + n] = sqrtf(fq * fq + fu * fu);
@@ -199,11 +214,13 @@ hipError_t launch_t(const rmsynth_plan_s& p, const ExecArgs& a)
     if (a.layout == RMSYNTH_LOS_MAJOR)
         hipLaunchKernelGGL((synth_split_kernel<RMSYNTH_LOS_MAJOR, FP16>), dim3((unsigned)blocks),
                            dim3(256), 0, a.stream, a.Q, a.U, a.nlos, a.ld, p.nchan, a.vec4 ? 1 : 0,
-                           p.d_b, p.d_w, nk, p.d_phi, p.nphi, tiles_n, K, a.Fq, a.Fu, a.Fabs);
+                           p.d_b, p.d_w, nk, p.d_phi, p.nphi, tiles_n, K, a.Fq, a.Fu, a.Fabs,
+                           a.los_scale);
     else
         hipLaunchKernelGGL((synth_split_kernel<RMSYNTH_FREQ_MAJOR, FP16>), dim3((unsigned)blocks),
                            dim3(256), 0, a.stream, a.Q, a.U, a.nlos, a.ld, p.nchan, a.vec4 ? 1 : 0,
-                           p.d_b, p.d_w, nk, p.d_phi, p.nphi, tiles_n, K, a.Fq, a.Fu, a.Fabs);
+                           p.d_b, p.d_w, nk, p.d_phi, p.nphi, tiles_n, K, a.Fq, a.Fu, a.Fabs,
+                           a.los_scale);
     return hipGetLastError();
 }
 

@@ -12,7 +12,7 @@ per-product bound 3 x 2^-16 (FP32 and FP16 stay at 1e-5).
 Also: a single component is a Faraday-thin screen (eqs. (1), (3)) exactly,
 the GPU forward and adjoint transforms satisfy <F(P), C> = <P, K w A(C)>, and
 the phase tables take the factored path when the channels are uniform in
-lambda^2 (FP16 allowed only there).
+lambda^2.
 """
 import numpy as np
 import pytest
@@ -101,15 +101,17 @@ def test_channels_uniform_in_lambda2_take_the_factored_tables(prec):
     _check(plan, C, lam, w, phi, prec, PREC_TOL[prec])
 
 
-def test_fp16_needs_channels_uniform_in_lambda2():
-    import torch
-    wl = WORKLOADS["c1"]
-    plan = rs.Plan(wl.lambda2(), wl.weights(), wl.phi())
-    C = torch.zeros((4, plan.nphi), dtype=torch.float32, device="cuda")
-    P = torch.empty((4, plan.nchan), dtype=torch.float32, device="cuda")
-    with pytest.raises(rs.RmsynthError) as ei:
-        rs.rmsynth_adjoint(plan.handle, C, C, 4, rs.RMSYNTH_SPLIT_FP16, P, P)
-    assert ei.value.code == rs.RMSYNTH_EUNSUPPORTED
+def test_fp16_on_channels_not_uniform_in_lambda2():
+    """The FP16 split on the per-element phase tiles (per-LOS scale, K after
+    the sums): any band."""
+    note("adjoint fp16 per-element")
+    wl = WORKLOADS["c3"]
+    lam, w = wl.lambda2(), wl.weights()
+    phi = np.linspace(-2000, 2000, 701)
+    plan = rs.Plan(lam, w, phi)
+    rng = np.random.default_rng(17)
+    C = _components(rng, 150, phi.size, "dense") * (10.0 ** rng.uniform(-4, 2, 150))[:, None]
+    _check(plan, C, lam, w, phi, "fp16x3", PREC_TOL["fp16x3"])
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])

@@ -381,7 +381,7 @@ def test_c4_full_size_sampled():
     _full_size("c4", ["fp16x3", "fp32", "bf16x3"], 2048)
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp16x3"])
 @pytest.mark.parametrize("layout", [LOS_MAJOR, FREQ_MAJOR], ids=["los", "freq"])
 def test_nonuniform_phi_grid(prec, layout):
     """An irregular phi grid takes the per-element phase generator instead of
@@ -398,42 +398,41 @@ def test_nonuniform_phi_grid(prec, layout):
            phi, layout, PREC_TOL[prec])
 
 
-def test_fp16_split_needs_uniform_grid_and_workspace():
-    """The FP16 split keeps a per-LOS scale in the caller's workspace and is
-    only offered on uniform phi grids."""
+def test_fp16_split_needs_its_workspace():
+    """The FP16 split keeps a per-LOS scale in the caller's workspace, on
+    uniform and irregular phi grids alike."""
     import torch
     c = make_small_cube(8, 32, 9, seed=2)
     Q = dev32(c["Q"])
     F = torch.empty((8, 40), dtype=torch.float32, device="cuda")
     rng = np.random.default_rng(3)
-    plan = rs.Plan(c["lambda2"], c["weights"], np.sort(rng.uniform(-50, 50, 40)))
-    with pytest.raises(rs.RmsynthError) as ei:
-        rs.rmsynth_execute(plan.handle, Q, Q, 8, LOS_MAJOR, rs.RMSYNTH_SPLIT_FP16, F, F)
-    assert ei.value.code == rs.rmsynth.RMSYNTH_EUNSUPPORTED
-    plan = rs.Plan(c["lambda2"], c["weights"], np.linspace(-50, 50, 40))
-    need = rs.rmsynth_workspace_size(plan.handle, 8, LOS_MAJOR, rs.RMSYNTH_SPLIT_FP16)
-    assert need >= 8 * 4
-    with pytest.raises(rs.RmsynthError) as ei:
-        rs.rmsynth_execute(plan.handle, Q, Q, 8, LOS_MAJOR, rs.RMSYNTH_SPLIT_FP16, F, F)
-    assert ei.value.code == rs.rmsynth.RMSYNTH_EWORKSPACE
-    small = torch.empty(4, dtype=torch.uint8, device="cuda")
-    with pytest.raises(rs.RmsynthError) as ei:
-        rs.rmsynth_execute(plan.handle, Q, Q, 8, LOS_MAJOR, rs.RMSYNTH_SPLIT_FP16, F, F,
-                           workspace=small, workspace_bytes=4)
-    assert ei.value.code == rs.rmsynth.RMSYNTH_EWORKSPACE
+    for phi in (np.sort(rng.uniform(-50, 50, 40)), np.linspace(-50, 50, 40)):
+        plan = rs.Plan(c["lambda2"], c["weights"], phi)
+        need = rs.rmsynth_workspace_size(plan.handle, 8, LOS_MAJOR, rs.RMSYNTH_SPLIT_FP16)
+        assert need >= 8 * 4
+        with pytest.raises(rs.RmsynthError) as ei:
+            rs.rmsynth_execute(plan.handle, Q, Q, 8, LOS_MAJOR, rs.RMSYNTH_SPLIT_FP16, F, F)
+        assert ei.value.code == rs.rmsynth.RMSYNTH_EWORKSPACE
+        small = torch.empty(4, dtype=torch.uint8, device="cuda")
+        with pytest.raises(rs.RmsynthError) as ei:
+            rs.rmsynth_execute(plan.handle, Q, Q, 8, LOS_MAJOR, rs.RMSYNTH_SPLIT_FP16, F, F,
+                               workspace=small, workspace_bytes=4)
+        assert ei.value.code == rs.rmsynth.RMSYNTH_EWORKSPACE
 
 
-def test_fp16_split_wide_dynamic_range():
-    """Per-LOS scaling: LOS whose values differ by 1e8 in size are all
-    transformed to FP32-like accuracy."""
-    note("fp16x3 dynamic range")
+@pytest.mark.parametrize("irregular", [False, True], ids=["uniform", "irregular"])
+def test_fp16_split_wide_dynamic_range_any_grid(irregular):
+    """Per-LOS scaling on either kernel family: LOS whose values differ by 1e8
+    in size are all transformed to FP32-like accuracy."""
+    note(f"fp16x3 dynamic range, irregular={irregular}")
     c = make_small_cube(96, 160, 257, seed=31, nsrc=10)
+    phi = np.sort(np.random.default_rng(4).uniform(-100, 100, 257)) if irregular else c["phi"]
     scales = 10.0 ** np.linspace(-6, 2, 96)
     Q = np.float32(c["Q"] * scales[:, None])
     U = np.float32(c["U"] * scales[:, None])
-    plan = rs.Plan(c["lambda2"], c["weights"], c["phi"])
+    plan = rs.Plan(c["lambda2"], c["weights"], phi)
     out = _run(plan, dev32(Q), dev32(U), LOS_MAJOR, rs.RMSYNTH_SPLIT_FP16)
-    _check(out, Q.astype(np.float64), U.astype(np.float64), c["lambda2"], c["weights"], c["phi"],
+    _check(out, Q.astype(np.float64), U.astype(np.float64), c["lambda2"], c["weights"], phi,
            LOS_MAJOR, PREC_TOL["fp16x3"])
 
 

@@ -69,7 +69,7 @@ def test_search_equals_execute_peaks_fit(prec, layout, nlos, nchan, nphi):
     assert out["idx"][2] >= 0
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("prec", list(PRECS))
 def test_search_on_a_nonuniform_grid(prec):
     """Unfused paths hold F of a batch in the workspace; same results."""
     note(f"search non-uniform grid {prec}")
