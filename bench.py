@@ -62,9 +62,10 @@ def paper_context():
 
 # HBM bytes per launch of the dominant kernel, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE counter runs scaled by a plain 1 GiB copy (FETCH x 2.0, WRITE x 1.0),
-# keyed by (workload, precision, sha256 prefix of the kernel source they were
+# keyed by (workload, precision, sha256 prefix of the kernel sources they were
 # taken on).  A changed kernel source reports null until counters are retaken.
-KERNEL_SRC = os.path.join(ROOT, "paper_1810_06250_amd", "csrc", "synth_factored.hip")
+KERNEL_SRC = [os.path.join(ROOT, "paper_1810_06250_amd", "csrc", f)
+              for f in ("synth_factored.hip", "common.h")]
 TRAFFIC = {
     ("c3", "bf16x3", "a29eb4f9e51cddcb"): 2.0 * 2382832 * 1024 + 1.0 * 16978369 * 1024,
 }
@@ -73,7 +74,10 @@ TRAFFIC = {
 def measured_traffic(workload, precision):
     import hashlib
     try:
-        digest = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+        h = hashlib.sha256()
+        for f in KERNEL_SRC:
+            h.update(open(f, "rb").read())
+        digest = h.hexdigest()[:16]
     except OSError:
         return None
     return TRAFFIC.get((workload, precision, digest))

@@ -233,9 +233,11 @@ size_t rmsynth_search_noalloc_scratch_bytes(void);
  * model Faraday dispersion function, come from here.
  *   Cq, Cu   [nlos][nphi] device float: Re and Im of the components.
  *   Pq, Pu   [nlos][nchan] device float (LOS-major): Re and Im of P.
- *   precision  any rmsynth_precision (the phase tiles are generated per
- *            element unless the channels are uniform in lambda^2, then the
- *            factored tables serve).
+ *   precision  any rmsynth_precision.  The split precisions take tables
+ *            instead of per-element phase generation when an axis is
+ *            uniform: channels uniform in lambda^2 (the factored tables of
+ *            the forward transform) or a uniform phi grid of at least 288
+ *            values (K-tiles of 96 phi combined by Horner's rule).
  *   workspace  rmsynth_adjoint_workspace_size() bytes (0 except FP16), or
  *            less down to its value for 128 LOS (batches).
  * Every channel gets a value (weights do not enter).  A LOS with a

@@ -46,7 +46,8 @@ void free_plan(rmsynth_plan_s* p)
     free_plan(p->adj);
     void* bufs[] = {p->d_b, p->d_lambda2, p->d_w, p->d_phi, p->d_base, p->d_Tbf[0], p->d_Tbf[1],
                     p->d_Thf[0], p->d_Thf[1], p->d_nufft_rot, p->d_nufft_off, p->d_nufft_ent,
-                    p->d_nufft_tw, p->d_nufft_deconv};
+                    p->d_nufft_tw, p->d_nufft_deconv, p->d_kw, p->d_kbase, p->d_krot,
+                    p->d_Kbf[0], p->d_Kbf[1], p->d_Khf[0], p->d_Khf[1]};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     delete p;
@@ -129,6 +130,37 @@ int build_adjoint_plan(rmsynth_plan_s* p, const double* lambda2, const double* p
         return rms_hip_fail(e, "rmsynth_plan: hipMemcpy (adjoint)");
     q->uniform = detect_uniform(hgrid.data(), q->nphi, amax, &q->phi0, &q->dphi);
     if (q->uniform) return build_factor_tables(q);
+    // A uniform phi grid makes the contracted axis uniform: the channel-factored
+    // tables then replace per-element phase generation (same phase tolerance,
+    // now over every output lambda^2).
+    double gmax = 0.0, phi0 = 0.0, dphi = 0.0;
+    for (int32_t j = 0; j < p->nchan; ++j) gmax = std::max(gmax, std::fabs(hgrid[j]));
+    if (p->nphi < 3 * kKTile || !detect_uniform(phi, p->nphi, gmax, &phi0, &dphi)) return RMSYNTH_OK;
+    q->cuniform = true;
+    q->kb0 = phi0 / M_PI;
+    q->kdb = dphi / M_PI;
+    {
+        constexpr int kc = 8, kts = kKTile / kc;  // K-step of the factored kernel
+        const int nk = (q->nchan + kc - 1) / kc;
+        q->kpad = ((nk + kts - 1) / kts * kts - nk) * kc;
+    }
+    const size_t nT = (size_t)(kKTile / 4) * q->nphi_pad;
+    if ((e = hipMalloc(&q->d_kw, sizeof(float2) * q->nchan_pad)) != hipSuccess ||
+        (e = hipMalloc(&q->d_kbase, sizeof(float2) * q->nphi_pad)) != hipSuccess ||
+        (e = hipMalloc(&q->d_krot, sizeof(float2) * q->nphi_pad)) != hipSuccess ||
+        (e = hipMalloc(&q->d_Kbf[0], sizeof(uint4) * nT)) != hipSuccess ||
+        (e = hipMalloc(&q->d_Kbf[1], sizeof(uint4) * nT)) != hipSuccess ||
+        (e = hipMalloc(&q->d_Khf[0], sizeof(uint4) * nT)) != hipSuccess ||
+        (e = hipMalloc(&q->d_Khf[1], sizeof(uint4) * nT)) != hipSuccess)
+        return rms_fail(RMSYNTH_ENOMEM, "rmsynth_plan: hipMalloc (adjoint tables): %s", hipGetErrorString(e));
+    hipStream_t s = nullptr;
+    if ((e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) != hipSuccess)
+        return rms_hip_fail(e, "rmsynth_plan: hipStreamCreate");
+    e = launch_kfactor_tables(*q, s);
+    hipError_t e2 = hipStreamSynchronize(s);
+    (void)hipStreamDestroy(s);
+    if (e != hipSuccess) return rms_hip_fail(e, "rmsynth_plan: adjoint-table kernel");
+    if (e2 != hipSuccess) return rms_hip_fail(e2, "rmsynth_plan: adjoint-table kernel");
     return RMSYNTH_OK;
 }
 
@@ -398,6 +430,8 @@ int run_execute(const rmsynth_plan_s* p, const float* Q, const float* U, int64_t
         hipError_t e;
         if (precision == RMSYNTH_FP32) e = launch_synth_fp32(*p, a);
         else if (p->uniform) e = launch_synth_factored(*p, a, precision);
+        else if (p->cuniform && layout == RMSYNTH_LOS_MAJOR && !parts && !recs)
+            e = launch_synth_kfactored(*p, a, precision);
         else e = launch_synth_split(*p, a, precision);
         if (e != hipSuccess) return rms_hip_fail(e, who);
         b0 += m;

@@ -44,6 +44,23 @@ struct rmsynth_plan_s {
     uint4* d_Tbf[2];
     uint4* d_Thf[2];
     bool any_flagged;    // some channel has weight 0
+    // Channel-factored tables (synth_factored.hip, KF), present when the
+    // contracted axis is uniform, b_j = kb0 + j kdb, and the output grid is
+    // not (the adjoint plan of a uniform phi grid).  K-tiles of kKTile
+    // channels, the lowest one starting kpad channels below channel 0:
+    //   d_kw    [nchan_pad] float2  (w_j, 0)
+    //   d_kbase [nphi_pad]  float2  K (cos, sin)(2 pi (kb0 - kpad kdb) g_k)
+    //   d_krot  [nphi_pad]  float2  (cos, sin)(2 pi kKTile kdb g_k)
+    //   d_K{bf,hf}[hi/lo] [kKTile/4][nphi_pad] uint4: 4 channels x (cos, sin)
+    //                   of 2 pi i kdb g_k, i = 0 .. kKTile-1, split into hi/lo
+    bool cuniform;
+    double kb0, kdb;
+    int32_t kpad;
+    float2* d_kw;
+    float2* d_kbase;
+    float2* d_krot;
+    uint4* d_Kbf[2];
+    uint4* d_Khf[2];
     // The adjoint transform's plan (axes exchanged, see build_adjoint_plan);
     // owned, NULL inside an adjoint plan itself.
     rmsynth_plan_s* adj;
@@ -66,6 +83,7 @@ hipError_t launch_nufft(const rmsynth_plan_s& p, const float* Q, const float* U,
                         float* Fq, float* Fu, float* Fabs, hipStream_t s);
 
 constexpr int kFactorTile = 128;  // phi per tile of the factored kernels
+constexpr int kKTile = 96;        // channels per K-tile of the channel-factored form
 
 constexpr int kChanPad = 32;    // channel padding granule (largest K-step)
 constexpr int kPhiPad = 256;    // phi padding granule (largest phi tile)
@@ -117,6 +135,9 @@ __device__ __forceinline__ uint32_t pack2_bf16(float a, float b)
 __device__ __forceinline__ void split2_bf16(float a, float b, uint32_t& hi, uint32_t& lo)
 {
     hi = pack2_bf16(a, b);
+    // Opaque to the optimiser: otherwise it re-converts a alone for hi << 16
+    // (one more conversion per pair) instead of reusing hi.
+    asm("" : "+v"(hi));
     const float ra = a - __uint_as_float(hi << 16);
     const float rb = b - __uint_as_float(hi & 0xffff0000u);
     lo = pack2_bf16(ra, rb);
@@ -219,6 +240,8 @@ hipError_t launch_synth_split(const rmsynth_plan_s& p, const ExecArgs& a, int pr
 hipError_t launch_synth_factored(const rmsynth_plan_s& p, const ExecArgs& a, int precision);
 hipError_t launch_los_scale(const rmsynth_plan_s& p, const ExecArgs& a);
 hipError_t launch_factor_tables(const rmsynth_plan_s& p, hipStream_t s);
+hipError_t launch_kfactor_tables(const rmsynth_plan_s& p, hipStream_t s);
+hipError_t launch_synth_kfactored(const rmsynth_plan_s& p, const ExecArgs& a, int precision);
 hipError_t launch_peaks(const rmsynth_plan_s& p, const float* Fq, const float* Fu, int64_t nlos,
                         int32_t* idx, float* phi_pk, float* amp, float* q_pk, float* u_pk,
                         hipStream_t s);

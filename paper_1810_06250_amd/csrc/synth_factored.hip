@@ -26,6 +26,20 @@
 // accumulators per lane), so two workgroups share a CU: while one waits on
 // memory, a barrier or its output stores, the other keeps the matrix cores
 // busy.  Q/U loads run two K-steps ahead of their use.
+//
+// The same kernel also serves plans whose contracted axis is uniform and
+// whose output grid is not (KF: the adjoint transform on a uniform phi grid,
+// where the phi_k are the contracted "channels" b_j = b_0 + j db).  With
+// K-tiles of KT = 96 channels starting at j_J = J KT - P (P channels of zero
+// padding below channel 0 make the top K-tile full), j = j_J + i,
+//   exp(-2 pi i b_j g_k) = base_k r_k^J T'_{i,k},  base_k = exp(-2 pi i (b_0 - P db) g_k),
+//   r_k = exp(-2 pi i KT db g_k),  T'_{i,k} = exp(-2 pi i i db g_k),
+// so F_k = K base_k sum_J r_k^J S_J(k) with S_J the contraction of K-tile J
+// against the table T' (KT x nphi, tile-independent).  The K-tiles are taken
+// from the top down and the accumulators are multiplied by r_k before each
+// new K-tile (Horner's rule), K base_k in the epilogue; the data are only
+// weighted and split, not rotated.  KT is a multiple of three K-steps, so
+// every K-tile starts at the same point of the loop's register rotation.
 #include <float.h>
 
 #include "common.h"
@@ -36,6 +50,8 @@ constexpr int MT = 128;          // LOS per tile
 constexpr int NT = kFactorTile;  // phi per tile
 constexpr int KC = 8;            // channels per K-step
 constexpr int NQ = KC / 4;       // channel quads per K-step
+constexpr int KTS = kKTile / KC;  // K-steps per K-tile (KF)
+static_assert(KTS % 3 == 0, "a K-tile holds whole blocks of three K-steps");
 
 struct ABuf {
     uint4 a_hi[NQ][MT];
@@ -93,15 +109,20 @@ __device__ __forceinline__ f32x16_t mfma16(uint4 a, uint4 b, f32x16_t c)
 // peak_merge_kernel, at part[half tile * part_ld + LOS].
 // PEAKS 2: F is not stored; the epilogue writes one PeakRec per (LOS, half
 // tile) instead, at rec[half tile * part_ld + LOS], for peak_merge_rec_kernel.
-template <int LAYOUT, bool FP16, bool FAST, bool FLAGS, int PEAKS>
+// KF: the K-tile form above; base then holds (w_j, 0) per channel, Thi/Tlo
+// hold T' as [KT/4][ldT] quads, kbase and krot the K base_k and r_k per
+// output (LOS-major input, no peaks).
+template <int LAYOUT, bool FP16, bool FAST, bool FLAGS, int PEAKS, bool KF>
 __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
     const float* __restrict__ Q, const float* __restrict__ U, int64_t nlos, int64_t ld,
     int nchan, const float2* __restrict__ base, const uint4* __restrict__ Thi,
     const uint4* __restrict__ Tlo, int nchan_pad, int nk, int nphi, int tiles_n,
     float* __restrict__ Fq, float* __restrict__ Fu, float* __restrict__ Fabs,
     const float* __restrict__ los_scale, PeakPart* __restrict__ part, int64_t part_ld,
-    PeakRec* __restrict__ rec, uint32_t neg_hi)
+    PeakRec* __restrict__ rec, uint32_t neg_hi, const float2* __restrict__ kbase,
+    const float2* __restrict__ krot, int ldT)
 {
+    static_assert(!KF || (PEAKS == 0 && LAYOUT == RMSYNTH_LOS_MAJOR), "KF: LOS-major, no peaks");
     // Triple-buffered A tiles (packed data) and T tiles (phase table), in one
     // block so that the epilogue can reuse all of it.
     struct Lds {
@@ -130,7 +151,36 @@ __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
     // FP16: per-LOS power-of-two scale that keeps both halves of the split in
     // half precision's normal range; undone exactly in the epilogue.
     const float lsc = FP16 ? los_scale[lr] : 1.0f;
-    const_f4_ptr bt = (const_f4_ptr)(base + (int64_t)tn * nchan_pad);
+    // KF on rows that allow no 16-byte loads (COAL): eight lanes share a LOS
+    // row, lane cc reading channel cc of the K-step, rows rq + 32 i (i < 4),
+    // so that a wave's load covers 8 rows x 32 contiguous bytes; the unit
+    // weights of the KF plans leave nothing to rotate.
+    constexpr bool COAL = KF && !FAST;
+    const int cc = t & 7, rq = t >> 3;
+    // Row offsets from the tile's first row (below 2^31: 128 rows).
+    const float* Qt = Q + (COAL ? l0 * ld : 0);
+    const float* Ut = U + (COAL ? l0 * ld : 0);
+    // Byte offsets from the tile's first row (a uniform base and a 32-bit
+    // offset per load); rows past the cube read the last LOS.
+    const uint32_t crow0 = (uint32_t)(rq * ld * 4), crow_step = (uint32_t)(32 * ld * 4);
+    const uint32_t crow_last = (uint32_t)(((nlos - 1 - l0) < MT ? (nlos - 1 - l0) : MT - 1) * ld * 4);
+    float csc[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int64_t g = l0 + rq + 32 * i;
+        csc[i] = COAL && FP16 ? los_scale[g < nlos ? g : nlos - 1] : 1.0f;
+    }
+    const_f4_ptr bt = (const_f4_ptr)(base + (KF ? 0 : (int64_t)tn * nchan_pad));
+    // KF: the K-step contracted at position k of the loop.  K-tile J covers
+    // K-steps J KTS - pad .. (J + 1) KTS - pad - 1; the full K-tiles come
+    // first, from the top down, then the valid K-steps of K-tile 0.
+    const int ntile = (nk + KTS - 1) / KTS;
+    const int pad = ntile * KTS - nk;
+    const int kfull = (ntile - 1) * KTS;
+    auto ks_of = [&](int k) {
+        if (!KF || k >= kfull) return KF ? k - kfull : k;
+        return (ntile - 1 - k / KTS) * KTS - pad + k % KTS;
+    };
 
     // Q/U and channel rotations of one K-step (4 channels of this thread),
     // held in registers; three sets rotate (see the K-loop below).
@@ -141,15 +191,24 @@ __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
     };
     Regs R0, R1, R2;
 
-    auto gload_rot = [&](Regs& R, int ks) {
+    auto gload_rot = [&](Regs& R, int k) __attribute__((always_inline)) {
+        if (COAL) return;
+        const int ks = ks_of(k);
         const int j0 = ks * KC + 4 * hh;
         R.rot[0] = bt[(j0 >> 1)];
         R.rot[1] = bt[(j0 >> 1) + 1];
     };
-    auto gload_vec = [&](Regs& R, int ks) {
+    auto gload_vec = [&](Regs& R, int k) __attribute__((always_inline)) {
+        const int ks = ks_of(k);
         const int j0 = ks * KC + 4 * hh;
-        R.th = Thi[(int64_t)ks * (NQ * NT) + t];
-        R.tl = Tlo[(int64_t)ks * (NQ * NT) + t];
+        if (KF) {
+            const int64_t at = (int64_t)(((ks + pad) % KTS) * NQ + (t >> 7)) * ldT + n0 + (t & 127);
+            R.th = Thi[at];
+            R.tl = Tlo[at];
+        } else {
+            R.th = Thi[(int64_t)ks * (NQ * NT) + t];
+            R.tl = Tlo[(int64_t)ks * (NQ * NT) + t];
+        }
         if (FAST) {
             if (LAYOUT == RMSYNTH_LOS_MAJOR) {
                 const float4 a = *reinterpret_cast<const float4*>(Q + lr * ld + j0);
@@ -163,6 +222,21 @@ __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
                     R.u[i] = U[(int64_t)(j0 + i) * ld + lr];
                 }
             }
+        } else if (COAL) {
+            // Channels past the end load the last one (in bounds) and read as 0;
+            // no branch, which keeps the register sets in registers.
+            const int j = ks * KC + cc;
+            const bool ok = j < nchan;
+            const uint32_t jb = 4u * (uint32_t)(ok ? j : nchan - 1);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const uint32_t ro = crow0 + i * crow_step;
+                const uint32_t off = (ro < crow_last ? ro : crow_last) + jb;
+                const float a = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(Qt) + off);
+                const float b = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(Ut) + off);
+                R.q[i] = ok ? a : 0.0f;
+                R.u[i] = ok ? b : 0.0f;
+            }
         } else {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
@@ -175,14 +249,18 @@ __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
         }
     };
 
-    auto gload = [&](Regs& R, int ks) {
+    auto gload = [&](Regs& R, int ks) __attribute__((always_inline)) {
         gload_vec(R, ks);
         gload_rot(R, ks);
     };
 
     // Channel i of the thread's 4: rotate, split.
     uint32_t hi[4], lo[4];
-    auto pack1 = [&](const Regs& R, int i) {
+    auto pack1 = [&](const Regs& R, int i) __attribute__((always_inline)) {
+        if constexpr (COAL) {
+            split2<FP16>(R.q[i] * csc[i], R.u[i] * csc[i], hi[i], lo[i]);
+            return;
+        }
         const f32x4_t rr = R.rot[i >> 1];
         const float rc = (i & 1) ? rr.z : rr.x;
         const float rs = (i & 1) ? rr.w : rr.y;
@@ -199,11 +277,19 @@ __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
         }
         split2<FP16>(xr, yr, hi[i], lo[i]);
     };
-    auto store_t = [&](BBuf& b, const Regs& R) {
+    auto store_t = [&](BBuf& b, const Regs& R) __attribute__((always_inline)) {
         (&b.b_hi[0][0])[t] = R.th;
         (&b.b_lo[0][0])[t] = R.tl;
     };
-    auto store_a = [&](ABuf& b) {
+    auto store_a = [&](ABuf& b) __attribute__((always_inline)) {
+        if constexpr (COAL) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                reinterpret_cast<uint32_t*>(&b.a_hi[cc >> 2][rq + 32 * i])[cc & 3] = hi[i];
+                reinterpret_cast<uint32_t*>(&b.a_lo[cc >> 2][rq + 32 * i])[cc & 3] = lo[i];
+            }
+            return;
+        }
         b.a_hi[hh][la] = make_uint4(hi[0], hi[1], hi[2], hi[3]);
         b.a_lo[hh][la] = make_uint4(lo[0], lo[1], lo[2], lo[3]);
     };
@@ -225,7 +311,7 @@ __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
     struct Frag {
         uint4 bh[2], bl[2], ah, al;
     };
-    auto load_frag = [&](Frag& F, const ABuf& a, const BBuf& b) {
+    auto load_frag = [&](Frag& F, const ABuf& a, const BBuf& b) __attribute__((always_inline)) {
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb) {
             F.bh[cb] = b.b_hi[hsel][64 * wc + 32 * cb + r];
@@ -240,7 +326,7 @@ __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
     // fragments are read ahead.
     // The real-part rows (x', y') of a LOS group come from LDS; the
     // imaginary-part rows (y', -x') are derived from them in registers.
-    auto mma = [&](const ABuf& cur, const Frag& F, const Regs& P) {
+    auto mma = [&](const ABuf& cur, const Frag& F, const Regs& P) __attribute__((always_inline)) {
         uint4 ah = F.ah, al = F.al;
 #pragma unroll
         for (int g = 0; g < 2; ++g) {
@@ -300,7 +386,26 @@ __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
     // stored).
     Frag F;
     int bc = 0;  // buffer of K-step k; (bc + 1) % 3 and (bc + 2) % 3 follow
-    auto step = [&](Regs& Rp, Regs& Rl, int k) {
+    // KF: r_k of this lane's two output columns; acc <- r acc (complex,
+    // Re in acc[g][0], Im in acc[g][1]) before each K-tile after the first.
+    float2 rr[2] = {make_float2(1.0f, 0.0f), make_float2(1.0f, 0.0f)};
+    if (KF) {
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) rr[cb] = krot[n0 + 64 * wc + 32 * cb + (lane & 31)];
+    }
+    auto rotate_acc = [&]() __attribute__((always_inline)) {
+#pragma unroll
+        for (int g = 0; g < 2; ++g)
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    const float a = acc[g][0][cb][v], b = acc[g][1][cb][v];
+                    acc[g][0][cb][v] = __builtin_fmaf(a, rr[cb].x, b * rr[cb].y);
+                    acc[g][1][cb][v] = __builtin_fmaf(b, rr[cb].x, -(a * rr[cb].y));
+                }
+    };
+    auto step = [&](Regs& Rp, Regs& Rl, int k) __attribute__((always_inline)) {
         const int bf = bc == 2 ? 0 : bc + 1;
         const int bn = bf == 2 ? 0 : bf + 1;
         const int kl = k + 4 < nk ? k + 4 : nk - 1;
@@ -342,12 +447,17 @@ __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
     sync_next();
     load_frag(F, abuf[0], bbuf[0]);
 
+    // KF: a K-tile boundary (every KTS K-steps, a multiple of three) falls at
+    // the top of a block of three K-steps or at the tail; the accumulators
+    // are rotated there.
     int k = 0;
     for (; k + 2 < nk; k += 3) {
+        if (KF && k > 0 && k % KTS == 0) rotate_acc();
         step(R0, R1, k);
         step(R2, R0, k + 1);
         step(R1, R2, k + 2);
     }
+    if (KF && k < nk && k > 0 && k % KTS == 0) rotate_acc();
     if (k < nk) step(R0, R1, k);
     if (k + 1 < nk) step(R2, R0, k + 1);
 
@@ -385,6 +495,21 @@ __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
                     }
                 }
             }
+    }
+    if constexpr (KF) {
+        // F = K base_k (sum over K-tiles), base_k K = (c, s) meaning c - i s.
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) {
+            const float2 bk = kbase[nc + 32 * cb];
+#pragma unroll
+            for (int g = 0; g < 2; ++g)
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    const float a = acc[g][0][cb][v], b = acc[g][1][cb][v];
+                    acc[g][0][cb][v] = __builtin_fmaf(a, bk.x, b * bk.y);
+                    acc[g][1][cb][v] = __builtin_fmaf(b, bk.x, -(a * bk.y));
+                }
+        }
     }
     if constexpr (PEAKS != 2) {
 #pragma unroll
@@ -704,11 +829,11 @@ hipError_t launch_t(const rmsynth_plan_s& p, const ExecArgs& a)
     const uint4* Tlo = FP16 ? p.d_Thf[1] : p.d_Tbf[1];
     const bool full_k = p.nchan % KC == 0;
     const bool fast = full_k && (a.layout != RMSYNTH_LOS_MAJOR || a.vec4);
-#define RMS_LAUNCH(L, F, G, P)                                                                        \
-    hipLaunchKernelGGL((synth_factored_kernel<L, FP16, F, G, P>), dim3((unsigned)blocks), dim3(256), 0, \
-                       a.stream, a.Q, a.U, a.nlos, a.ld, p.nchan, p.d_base, Thi, Tlo,                  \
-                       p.nchan_pad, nk, p.nphi, tiles_n, a.Fq, a.Fu, a.Fabs, a.los_scale, a.peak_part,  \
-                       a.peak_part_ld, a.peak_rec, 0x80000000u)
+#define RMS_LAUNCH(L, F, G, P)                                                                           \
+    hipLaunchKernelGGL((synth_factored_kernel<L, FP16, F, G, P, false>), dim3((unsigned)blocks), dim3(256), \
+                       0, a.stream, a.Q, a.U, a.nlos, a.ld, p.nchan, p.d_base, Thi, Tlo, p.nchan_pad, nk,  \
+                       p.nphi, tiles_n, a.Fq, a.Fu, a.Fabs, a.los_scale, a.peak_part, a.peak_part_ld,      \
+                       a.peak_rec, 0x80000000u, nullptr, nullptr, 0)
 #define RMS_LAUNCH_P(L, F, G)                         \
     do {                                              \
         if (a.peak_rec) RMS_LAUNCH(L, F, G, 2);       \
@@ -733,7 +858,88 @@ hipError_t launch_t(const rmsynth_plan_s& p, const ExecArgs& a)
     return hipGetLastError();
 }
 
+// The channel-factored form (KF): LOS-major input, F stored, no peaks.
+template <bool FP16>
+hipError_t launch_kf(const rmsynth_plan_s& p, const ExecArgs& a)
+{
+    const int tiles_n = (p.nphi + NT - 1) / NT;
+    const int nk = (p.nchan + KC - 1) / KC;
+    const int64_t tiles_m = (a.nlos + MT - 1) / MT;
+    const int64_t blocks = tiles_m * tiles_n;
+    if (blocks <= 0) return hipSuccess;
+    const uint4* Thi = FP16 ? p.d_Khf[0] : p.d_Kbf[0];
+    const uint4* Tlo = FP16 ? p.d_Khf[1] : p.d_Kbf[1];
+    const bool fast = p.nchan % KC == 0 && a.vec4;
+#define RMS_LAUNCH_KF(F, G)                                                                              \
+    hipLaunchKernelGGL((synth_factored_kernel<RMSYNTH_LOS_MAJOR, FP16, F, G, 0, true>), dim3((unsigned)blocks), \
+                       dim3(256), 0, a.stream, a.Q, a.U, a.nlos, a.ld, p.nchan, p.d_kw, Thi, Tlo,        \
+                       p.nchan_pad, nk, p.nphi, tiles_n, a.Fq, a.Fu, a.Fabs, a.los_scale, nullptr,       \
+                       (int64_t)0, nullptr, 0x80000000u, p.d_kbase, p.d_krot, p.nphi_pad)
+    if (fast) {
+        if (p.any_flagged) RMS_LAUNCH_KF(true, true);
+        else RMS_LAUNCH_KF(true, false);
+    } else {
+        if (p.any_flagged) RMS_LAUNCH_KF(false, true);
+        else RMS_LAUNCH_KF(false, false);
+    }
+#undef RMS_LAUNCH_KF
+    return hipGetLastError();
+}
+
+// Tables of the channel-factored form (FP64 argument reduction, FP32 sin/cos):
+//   T'[i/4][k] (4 channels x (cos, sin)(2 pi i db g_k), split), kbase_k, krot_k,
+//   kw_j = (w_j, 0).
+__global__ void kfactor_tables_kernel(const double* __restrict__ g, const float* __restrict__ wj,
+                                      int nphi_pad, int nchan_pad, double b0, double db, int kpad,
+                                      double K,
+                                      float2* __restrict__ kw, float2* __restrict__ kbase,
+                                      float2* __restrict__ krot, uint4* __restrict__ bf_hi,
+                                      uint4* __restrict__ bf_lo, uint4* __restrict__ hf_hi,
+                                      uint4* __restrict__ hf_lo)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nT = (int64_t)(kKTile / 4) * nphi_pad;
+    if (idx < nT) {
+        const int quad = (int)(idx / nphi_pad), k = (int)(idx % nphi_pad);
+        uint32_t bh[4], bl[4], hh[4], hl[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            float c, sn;
+            phase_cos_sin((double)(4 * quad + e) * db * g[k], c, sn);
+            split2_bf16(c, sn, bh[e], bl[e]);
+            split2_f16(c, sn, hh[e], hl[e]);
+        }
+        bf_hi[idx] = make_uint4(bh[0], bh[1], bh[2], bh[3]);
+        bf_lo[idx] = make_uint4(bl[0], bl[1], bl[2], bl[3]);
+        hf_hi[idx] = make_uint4(hh[0], hh[1], hh[2], hh[3]);
+        hf_lo[idx] = make_uint4(hl[0], hl[1], hl[2], hl[3]);
+    }
+    if (idx < nphi_pad) {
+        float c, sn;
+        phase_cos_sin((b0 - (double)kpad * db) * g[idx], c, sn);
+        kbase[idx] = make_float2((float)K * c, (float)K * sn);
+        phase_cos_sin((double)kKTile * db * g[idx], c, sn);
+        krot[idx] = make_float2(c, sn);
+    }
+    if (idx < nchan_pad) kw[idx] = make_float2(wj[idx], 0.0f);
+}
+
 }  // namespace
+
+hipError_t launch_synth_kfactored(const rmsynth_plan_s& p, const ExecArgs& a, int precision)
+{
+    return precision == RMSYNTH_SPLIT_FP16 ? launch_kf<true>(p, a) : launch_kf<false>(p, a);
+}
+
+hipError_t launch_kfactor_tables(const rmsynth_plan_s& p, hipStream_t stream)
+{
+    const int64_t nT = (int64_t)(kKTile / 4) * p.nphi_pad;
+    const int64_t n = std::max<int64_t>(nT, std::max(p.nphi_pad, p.nchan_pad));
+    hipLaunchKernelGGL(kfactor_tables_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream,
+                       p.d_phi, p.d_w, p.nphi_pad, p.nchan_pad, p.kb0, p.kdb, p.kpad, p.K, p.d_kw, p.d_kbase,
+                       p.d_krot, p.d_Kbf[0], p.d_Kbf[1], p.d_Khf[0], p.d_Khf[1]);
+    return hipGetLastError();
+}
 
 hipError_t launch_los_scale(const rmsynth_plan_s& p, const ExecArgs& a)
 {

@@ -10,9 +10,9 @@ forward transform's grids of a few phi, the error is taken relative to
 max(max_j |P|, sqrt(sum_k |C_k|^2)) and the bfloat16 split is held to its
 per-product bound 3 x 2^-16 (FP32 and FP16 stay at 1e-5).
 Also: a single component is a Faraday-thin screen (eqs. (1), (3)) exactly,
-the GPU forward and adjoint transforms satisfy <F(P), C> = <P, K w A(C)>, and
-the phase tables take the factored path when the channels are uniform in
-lambda^2.
+the GPU forward and adjoint transforms satisfy <F(P), C> = <P, K w A(C)>, the
+phase tables take the factored path when the channels are uniform in lambda^2,
+and a uniform phi grid takes the channel-factored form (K-tiles of phi).
 """
 import numpy as np
 import pytest
@@ -98,6 +98,23 @@ def test_channels_uniform_in_lambda2_take_the_factored_tables(prec):
     phi = np.linspace(-1000, 1000, 1501)
     plan = rs.Plan(lam, w, phi)
     C = _components(np.random.default_rng(8), 200, phi.size, "dense")
+    _check(plan, C, lam, w, phi, prec, PREC_TOL[prec])
+
+
+@pytest.mark.parametrize("prec", list(PRECS))
+@pytest.mark.parametrize("nphi", [288, 289, 1024, 1100])
+def test_adjoint_channel_factored_tiles(prec, nphi):
+    """A uniform phi grid of at least three K-tiles (96 phi each) takes the
+    channel-factored form: Horner's rule over K-tiles, the partial K-tile
+    padded below phi_0.  288 and 1024 fill whole K-steps (1024: 16-byte
+    aligned rows, vector loads), 289 and 1100 leave ragged ones."""
+    note(f"adjoint K-tiles nphi={nphi} {prec}")
+    wl = WORKLOADS["c2"]
+    lam, w = wl.lambda2(), wl.weights()
+    phi = np.linspace(-300.0, 300.0, nphi)
+    plan = rs.Plan(lam, w, phi)
+    rng = np.random.default_rng(nphi)
+    C = _components(rng, 200, nphi, "dense") * (10.0 ** rng.uniform(-3, 1, 200))[:, None]
     _check(plan, C, lam, w, phi, prec, PREC_TOL[prec])
 
 
