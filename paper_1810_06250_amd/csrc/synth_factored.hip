@@ -42,6 +42,8 @@
 // every K-tile starts at the same point of the loop's register rotation.
 #include <float.h>
 
+#include <type_traits>
+
 #include "common.h"
 
 namespace {
@@ -128,6 +130,7 @@ __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
     struct Lds {
         ABuf a[3];
         BBuf b[3];
+        float2 krot[KF ? NT : 1];  // KF: r_k of the tile's outputs
     };
     __shared__ Lds lds;
     ABuf* const abuf = lds.a;
@@ -178,34 +181,37 @@ __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
     const int pad = ntile * KTS - nk;
     const int kfull = (ntile - 1) * KTS;
     auto ks_of = [&](int k) {
-        if (!KF || k >= kfull) return KF ? k - kfull : k;
-        return (ntile - 1 - k / KTS) * KTS - pad + k % KTS;
+        if (!KF) return k;
+        const int top = (ntile - 1 - k / KTS) * KTS - pad + k % KTS;
+        return k < kfull ? top : k - kfull;  // a select: no branch around the loads
     };
 
     // Q/U and channel rotations of one K-step (4 channels of this thread),
     // held in registers; three sets rotate (see the K-loop below).
-    struct Regs {
+    struct RegsRot {
         float q[4], u[4];
         f32x4_t rot[2];  // K w_j (cos, sin) of theta_{j,k0}, 2 channels per vector
         uint4 th, tl;    // this thread's 16-byte share of the K-step's T tile
     };
+    struct RegsCoal {    // COAL: nothing to rotate
+        float q[4], u[4];
+        uint4 th, tl;
+    };
+    using Regs = typename std::conditional<COAL, RegsCoal, RegsRot>::type;
     Regs R0, R1, R2;
 
     auto gload_rot = [&](Regs& R, int k) __attribute__((always_inline)) {
-        if (COAL) return;
-        const int ks = ks_of(k);
-        const int j0 = ks * KC + 4 * hh;
-        R.rot[0] = bt[(j0 >> 1)];
-        R.rot[1] = bt[(j0 >> 1) + 1];
+        if constexpr (!COAL) {
+            const int ks = ks_of(k);
+            const int j0 = ks * KC + 4 * hh;
+            R.rot[0] = bt[(j0 >> 1)];
+            R.rot[1] = bt[(j0 >> 1) + 1];
+        }
     };
     auto gload_vec = [&](Regs& R, int k) __attribute__((always_inline)) {
         const int ks = ks_of(k);
         const int j0 = ks * KC + 4 * hh;
-        if (KF) {
-            const int64_t at = (int64_t)(((ks + pad) % KTS) * NQ + (t >> 7)) * ldT + n0 + (t & 127);
-            R.th = Thi[at];
-            R.tl = Tlo[at];
-        } else {
+        if (!KF) {
             R.th = Thi[(int64_t)ks * (NQ * NT) + t];
             R.tl = Tlo[(int64_t)ks * (NQ * NT) + t];
         }
@@ -259,27 +265,36 @@ __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
     auto pack1 = [&](const Regs& R, int i) __attribute__((always_inline)) {
         if constexpr (COAL) {
             split2<FP16>(R.q[i] * csc[i], R.u[i] * csc[i], hi[i], lo[i]);
-            return;
+        } else {
+            const f32x4_t rr = R.rot[i >> 1];
+            const float rc = (i & 1) ? rr.z : rr.x;
+            const float rs = (i & 1) ? rr.w : rr.y;
+            float xr = __builtin_fmaf(R.q[i], rc, R.u[i] * rs);
+            float yr = __builtin_fmaf(R.u[i], rc, -(R.q[i] * rs));
+            if (FLAGS) {
+                const bool flagged = ((__float_as_uint(rc) | __float_as_uint(rs)) << 1) == 0u;
+                xr = flagged ? 0.0f : xr;
+                yr = flagged ? 0.0f : yr;
+            }
+            if (FP16) {
+                xr *= lsc;
+                yr *= lsc;
+            }
+            split2<FP16>(xr, yr, hi[i], lo[i]);
         }
-        const f32x4_t rr = R.rot[i >> 1];
-        const float rc = (i & 1) ? rr.z : rr.x;
-        const float rs = (i & 1) ? rr.w : rr.y;
-        float xr = __builtin_fmaf(R.q[i], rc, R.u[i] * rs);
-        float yr = __builtin_fmaf(R.u[i], rc, -(R.q[i] * rs));
-        if (FLAGS) {
-            const bool flagged = ((__float_as_uint(rc) | __float_as_uint(rs)) << 1) == 0u;
-            xr = flagged ? 0.0f : xr;
-            yr = flagged ? 0.0f : yr;
-        }
-        if (FP16) {
-            xr *= lsc;
-            yr *= lsc;
-        }
-        split2<FP16>(xr, yr, hi[i], lo[i]);
     };
     auto store_t = [&](BBuf& b, const Regs& R) __attribute__((always_inline)) {
         (&b.b_hi[0][0])[t] = R.th;
         (&b.b_lo[0][0])[t] = R.tl;
+    };
+    // KF: the T' tile of the K-step at position k, loaded in the K-step that
+    // stores it (T' is small and stays in L2), which keeps it out of the
+    // register sets that hold loads two K-steps ahead.
+    auto load_tk = [&](Regs& R, int k) __attribute__((always_inline)) {
+        const int ks = ks_of(k < nk ? k : nk - 1);
+        const int64_t at = (int64_t)(((ks + pad) % KTS) * NQ + (t >> 7)) * ldT + n0 + (t & 127);
+        R.th = Thi[at];
+        R.tl = Tlo[at];
     };
     auto store_a = [&](ABuf& b) __attribute__((always_inline)) {
         if constexpr (COAL) {
@@ -386,14 +401,14 @@ __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
     // stored).
     Frag F;
     int bc = 0;  // buffer of K-step k; (bc + 1) % 3 and (bc + 2) % 3 follow
-    // KF: r_k of this lane's two output columns; acc <- r acc (complex,
-    // Re in acc[g][0], Im in acc[g][1]) before each K-tile after the first.
-    float2 rr[2] = {make_float2(1.0f, 0.0f), make_float2(1.0f, 0.0f)};
-    if (KF) {
-#pragma unroll
-        for (int cb = 0; cb < 2; ++cb) rr[cb] = krot[n0 + 64 * wc + 32 * cb + (lane & 31)];
-    }
+    // KF: acc <- r acc (complex, Re in acc[g][0], Im in acc[g][1]) before
+    // each K-tile after the first, r_k of this lane's two output columns read
+    // from the tile's copy in LDS (written before the prologue's barrier), so
+    // that they hold no registers across the loop.
     auto rotate_acc = [&]() __attribute__((always_inline)) {
+        float2 rr[2];
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) rr[cb] = lds.krot[64 * wc + 32 * cb + (lane & 31)];
 #pragma unroll
         for (int g = 0; g < 2; ++g)
 #pragma unroll
@@ -409,6 +424,7 @@ __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
         const int bf = bc == 2 ? 0 : bc + 1;
         const int bn = bf == 2 ? 0 : bf + 1;
         const int kl = k + 4 < nk ? k + 4 : nk - 1;
+        if (KF) load_tk(Rp, k + 2);
         gload_vec(Rl, kl);
         __builtin_amdgcn_sched_barrier(0);
         mma(abuf[bc], F, Rp);
@@ -432,15 +448,18 @@ __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
     // Prologue: K-steps 0 and 1 packed into buffers 0 and 1, K-steps 2 and 3
     // loading into R0 and R2, the first fragments of K-step 0 read after the
     // barrier.
+    if (KF && t < NT) lds.krot[t] = krot[n0 + t];
     gload(R0, 0);
     gload(R1, nk > 1 ? 1 : 0);
 #pragma unroll
     for (int i = 0; i < 4; ++i) pack1(R0, i);
     store_a(abuf[0]);
+    if (KF) load_tk(R0, 0);
     store_t(bbuf[0], R0);
 #pragma unroll
     for (int i = 0; i < 4; ++i) pack1(R1, i);
     store_a(abuf[1]);
+    if (KF) load_tk(R1, nk > 1 ? 1 : 0);
     store_t(bbuf[1], R1);
     gload(R0, nk > 2 ? 2 : nk - 1);
     gload(R2, nk > 3 ? 3 : nk - 1);
