@@ -67,7 +67,7 @@ def paper_context():
 KERNEL_SRC = [os.path.join(ROOT, "paper_1810_06250_amd", "csrc", f)
               for f in ("synth_factored.hip", "common.h")]
 TRAFFIC = {
-    ("c3", "bf16x3", "a29eb4f9e51cddcb"): 2.0 * 2382832 * 1024 + 1.0 * 16978369 * 1024,
+    ("c3", "bf16x3", "d2a17c9a3a307725"): 2.0 * 2394450.5 * 1024 + 1.0 * 17027976.5 * 1024,
 }
 
 
