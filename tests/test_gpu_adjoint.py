@@ -19,7 +19,7 @@ import pytest
 
 import oracle
 import paper_1810_06250_amd as rs
-from synthetic import WORKLOADS, band_lambda2, thin_spectrum, LOS_MAJOR
+from synthetic import WORKLOADS, band_lambda2, make_cube, stratified_subsample, thin_spectrum, LOS_MAJOR
 from gpu_util import PREC_TOL, SCALE_TOL, dev32, host, note
 
 pytestmark = pytest.mark.gpu
@@ -189,3 +189,34 @@ def test_nonfinite_component_poisons_only_its_los():
     keep = np.arange(10) != 4
     np.testing.assert_array_equal(b[0][keep], a[0][keep])
     np.testing.assert_array_equal(b[1][keep], a[1][keep])
+
+
+def test_adjoint_c3_full_size_sampled():
+    """The benchmark's adjoint launch: the c3 cube's F (1 048 576 LOS x 2001
+    phi, from the split transform) to its 400 channels in one call per
+    precision (bf16x3 and fp16x3 on the channel-factored form, FP32), checked
+    against the oracle on 256 sampled LOS (half of them with sources)."""
+    import torch
+    wl = WORKLOADS["c3"]
+    note("adjoint c3 full size")
+    cube = make_cube(wl, device="cuda")
+    lam, w, phi = cube["lambda2"], cube["weights"], cube["phi"]
+    plan = rs.Plan(lam, w, phi)
+    Fq, Fu, _ = plan.execute(cube["Q"], cube["U"], LOS_MAJOR, rs.RMSYNTH_SPLIT_BF16)
+    src = cube["src_los"]
+    del cube
+    torch.cuda.empty_cache()
+    sub = stratified_subsample(wl.nlos, src, 256, seed=wl.seed + 5)
+    subt = torch.as_tensor(sub, device="cuda")
+    Cq, Cu = host(Fq[subt]), host(Fu[subt])
+    rq, ru = oracle.adjoint(Cq, Cu, lam, w, phi)
+    for prec in ("bf16x3", "fp16x3", "fp32"):
+        Pq, Pu = plan.adjoint(Fq, Fu, PRECS[prec])
+        torch.cuda.synchronize()
+        assert Pq.shape == (wl.nlos, lam.size)
+        err = oracle.per_los_error(host(Pq[subt]), host(Pu[subt]), rq, ru)
+        note(f"  adjoint c3 {prec}: max per-LOS error {err.max():.3e}")
+        assert np.all(np.isfinite(err)) and err.max() <= PREC_TOL[prec]
+        del Pq, Pu
+        torch.cuda.empty_cache()
+    plan.close()

@@ -13,7 +13,7 @@ import pytest
 import oracle
 from oracle import nufft as onufft
 import paper_1810_06250_amd as rs
-from synthetic import WORKLOADS, make_cube, make_small_cube
+from synthetic import WORKLOADS, make_cube, make_small_cube, stratified_subsample
 from gpu_util import dev32, host, note
 
 pytestmark = pytest.mark.gpu
@@ -96,3 +96,32 @@ def test_nufft_unsupported():
         with pytest.raises(rs.RmsynthError) as ei:
             rs.rmsynth_execute_nufft(plan.handle, Q, Q, 4, F, F)
         assert ei.value.code == rs.RMSYNTH_EUNSUPPORTED
+
+
+def test_nufft_c3_full_size_sampled():
+    """The benchmark's NUFFT launch: the whole c3 cube (1 048 576 LOS) in one
+    call; 512 sampled LOS (half with sources) against the direct-sum and the
+    NUFFT oracles, and their peaks."""
+    import torch
+    wl = WORKLOADS["c3"]
+    note("nufft c3 full size")
+    cube = make_cube(wl, device="cuda")
+    lam, w, phi = cube["lambda2"], cube["weights"], cube["phi"]
+    plan = rs.Plan(lam, w, phi)
+    Fq, Fu, _ = plan.execute_nufft(cube["Q"], cube["U"])
+    torch.cuda.synchronize()
+    sub = stratified_subsample(wl.nlos, cube["src_los"], 512, seed=wl.seed + 7)
+    subt = torch.as_tensor(sub, device="cuda")
+    Q64 = host(cube["Q"][subt]).astype(np.float64)
+    U64 = host(cube["U"][subt]).astype(np.float64)
+    gq, gu = host(Fq[subt]), host(Fu[subt])
+    rq, ru = oracle.fdf(Q64, U64, lam, w, phi)
+    nq, nu = onufft.fdf_nufft(Q64, U64, lam, w, phi)
+    e_direct = oracle.per_los_error(gq, gu, rq, ru)
+    e_nufft = oracle.per_los_error(gq, gu, nq, nu)
+    note(f"  nufft c3: max per-LOS error {e_direct.max():.3e} (direct), {e_nufft.max():.3e} (oracle NUFFT)")
+    assert e_direct.max() <= 1e-5 and e_nufft.max() <= 1e-5
+    pk = plan.peaks(Fq, Fu)
+    nun, mism, bad = oracle.peak_agreement(host(pk["idx"])[sub], rq, ru, oracle.peaks(rq, ru, phi))
+    assert mism == 0 and bad == 0, (mism, nun, bad)
+    plan.close()

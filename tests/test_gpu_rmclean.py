@@ -23,8 +23,8 @@ import pytest
 import oracle
 from oracle import rmclean as orc
 import paper_1810_06250_amd as rs
-from synthetic import (band_lambda2, flag_channels, noise_sigma_F, slab_spectrum, thin_spectrum,
-                       LOS_MAJOR)
+from synthetic import (WORKLOADS, band_lambda2, flag_channels, make_cube, noise_sigma_F,
+                       slab_spectrum, stratified_subsample, thin_spectrum, LOS_MAJOR)
 from gpu_util import dev32, host, note
 
 pytestmark = pytest.mark.gpu
@@ -80,9 +80,15 @@ def _run(lam, w, phi, Fq, Fu, gain, cutoff, max_iter, fwhm=float("nan")):
 
 
 def _compare(lam, w, phi, Fq, Fu, gain, cutoff, max_iter):
+    g = _run(lam, w, phi, Fq, Fu, gain, cutoff, max_iter)
+    return _verify(lam, w, phi, Fq, Fu, g, gain, cutoff, max_iter)
+
+
+def _verify(lam, w, phi, Fq, Fu, g, gain, cutoff, max_iter):
+    """The checks of the module docstring on GPU outputs g (host arrays) of the
+    LOS whose input spectra are Fq, Fu."""
     eps_R, R2, dphi = _table_error(lam, w, phi)
     fwhm, _ = oracle.plan_info(lam, w)
-    g = _run(lam, w, phi, Fq, Fu, gain, cutoff, max_iter)
     ref = orc.rmclean(Fq.astype(np.float64), Fu.astype(np.float64), R2, dphi, gain, cutoff,
                       max_iter, fwhm)
     N = phi.size
@@ -210,3 +216,31 @@ def test_rmclean_in_place_and_argument_errors():
         rs.rmsynth_rmclean(wide.handle, F, F, 2, 0.1, 0.01, 10, 0.0, F, F, F.clone(), F.clone(),
                            workspace=ws, workspace_bytes=nb)
     assert ei.value.code == rs.RMSYNTH_EUNSUPPORTED
+
+
+def test_rmclean_c3_full_size_sampled():
+    """The benchmark's RM-CLEAN launch: the c3 cube's F (1 048 576 LOS x 2001
+    phi, from the split transform) in one call with the benchmark's settings
+    (gain 0.1, cutoff 5 sigma_F, at most 1000 iterations); 96 sampled LOS (half
+    with sources) checked against the oracle as above."""
+    import torch
+    wl = WORKLOADS["c3"]
+    note("rmclean c3 full size")
+    cube = make_cube(wl, device="cuda")
+    lam, w, phi = cube["lambda2"], cube["weights"], cube["phi"]
+    plan = rs.Plan(lam, w, phi)
+    Fq, Fu, _ = plan.execute(cube["Q"], cube["U"], LOS_MAJOR, rs.RMSYNTH_SPLIT_BF16)
+    src = cube["src_los"]
+    del cube
+    torch.cuda.empty_cache()
+    cutoff = 5 * noise_sigma_F(wl.sigma, w)
+    o = plan.rmclean(Fq, Fu, 0.1, cutoff, 1000, float("nan"))
+    torch.cuda.synchronize()
+    sub = stratified_subsample(wl.nlos, src, 96, seed=wl.seed + 9)
+    subt = torch.as_tensor(sub, device="cuda")
+    g = {k: host(v[subt]) for k, v in o.items()}
+    fq, fu = host(Fq[subt]), host(Fu[subt])
+    del o
+    plan.close()
+    g2, ref = _verify(lam, w, phi, fq, fu, g, 0.1, cutoff, 1000)
+    assert np.sum(ref["niter"] > 0) >= 40      # the source LOS are cleaned
