@@ -67,7 +67,7 @@ def paper_context():
 KERNEL_SRC = [os.path.join(ROOT, "paper_1810_06250_amd", "csrc", f)
               for f in ("synth_factored.hip", "common.h")]
 TRAFFIC = {
-    ("c3", "bf16x3", "d2a17c9a3a307725"): 2.0 * 2394450.5 * 1024 + 1.0 * 17027976.5 * 1024,
+    ("c3", "bf16x3", "bad4bffb574e7b5e"): 2.0 * 2389781.5 * 1024 + 1.0 * 16985156.5 * 1024,
 }
 
 

@@ -156,15 +156,15 @@ __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
     const float lsc = FP16 ? los_scale[lr] : 1.0f;
     // KF on rows that allow no 16-byte loads (COAL): eight lanes share a LOS
     // row, lane cc reading channel cc of the K-step, rows rq + 32 i (i < 4),
-    // so that a wave's load covers 8 rows x 32 contiguous bytes; the unit
-    // weights of the KF plans leave nothing to rotate.
+    // so that a wave's load covers 8 rows x 32 contiguous bytes.  The KF
+    // plans (adjoint plans) have unit weights and no flagged channel, so
+    // nothing is weighted or rotated.  Loads take the tile's first row as a
+    // uniform base and a 32-bit byte offset (128 rows: far below 2^32); rows
+    // past the cube read the last LOS.
     constexpr bool COAL = KF && !FAST;
     const int cc = t & 7, rq = t >> 3;
-    // Row offsets from the tile's first row (below 2^31: 128 rows).
     const float* Qt = Q + (COAL ? l0 * ld : 0);
     const float* Ut = U + (COAL ? l0 * ld : 0);
-    // Byte offsets from the tile's first row (a uniform base and a 32-bit
-    // offset per load); rows past the cube read the last LOS.
     const uint32_t crow0 = (uint32_t)(rq * ld * 4), crow_step = (uint32_t)(32 * ld * 4);
     const uint32_t crow_last = (uint32_t)(((nlos - 1 - l0) < MT ? (nlos - 1 - l0) : MT - 1) * ld * 4);
     float csc[4];
@@ -889,18 +889,15 @@ hipError_t launch_kf(const rmsynth_plan_s& p, const ExecArgs& a)
     const uint4* Thi = FP16 ? p.d_Khf[0] : p.d_Kbf[0];
     const uint4* Tlo = FP16 ? p.d_Khf[1] : p.d_Kbf[1];
     const bool fast = p.nchan % KC == 0 && a.vec4;
+    // KF plans (adjoint plans) weight every channel 1: the flag-free forms.
+    if (p.any_flagged) return hipErrorInvalidValue;
 #define RMS_LAUNCH_KF(F, G)                                                                              \
     hipLaunchKernelGGL((synth_factored_kernel<RMSYNTH_LOS_MAJOR, FP16, F, G, 0, true>), dim3((unsigned)blocks), \
                        dim3(256), 0, a.stream, a.Q, a.U, a.nlos, a.ld, p.nchan, p.d_kw, Thi, Tlo,        \
                        p.nchan_pad, nk, p.nphi, tiles_n, a.Fq, a.Fu, a.Fabs, a.los_scale, nullptr,       \
                        (int64_t)0, nullptr, 0x80000000u, p.d_kbase, p.d_krot, p.nphi_pad)
-    if (fast) {
-        if (p.any_flagged) RMS_LAUNCH_KF(true, true);
-        else RMS_LAUNCH_KF(true, false);
-    } else {
-        if (p.any_flagged) RMS_LAUNCH_KF(false, true);
-        else RMS_LAUNCH_KF(false, false);
-    }
+    if (fast) RMS_LAUNCH_KF(true, false);
+    else RMS_LAUNCH_KF(false, false);
 #undef RMS_LAUNCH_KF
     return hipGetLastError();
 }
