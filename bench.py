@@ -98,7 +98,7 @@ def parse():
     ap.add_argument("--gate-train", type=int, default=1_000_000)
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the other workloads (c1, c2, c4), the peaks-only search, the "
-                         "adjoint transform and RM-CLEAN")
+                         "NUFFT, the adjoint transform, RM-CLEAN and the irregular-grid leg")
     ap.add_argument("--no-gemm-ref", action="store_true",
                     help="skip timing the vendor bf16 GEMM used as a practical MFMA reference")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -437,6 +437,50 @@ def nufft_leg(rs, plan, cube, sub, steps):
     return res
 
 
+def nonuniform_leg(rs, cube, sub, steps):
+    """The same cube on an irregular phi grid (each phi of the workload moved by
+    up to +-0.2 of its step, seeded): the split precisions then generate the
+    phase tiles per element (synth_split_kernel), FP32 as before.  One step =
+    rmsynth_execute + rmsynth_peaks; errors against the FP64 oracle on the
+    stratified subsample."""
+    import torch
+    phi = np.asarray(cube["phi"], dtype=np.float64)
+    step = float(phi[1] - phi[0])
+    rng = np.random.default_rng(1810)
+    phi2 = phi + rng.uniform(-0.2 * step, 0.2 * step, phi.size)
+    cube2 = dict(cube, phi=phi2)
+    plan = rs.Plan(cube["lambda2"], cube["weights"], phi2)
+    nlos, nphi = cube["nlos"], phi2.size
+    samples = nlos * len(cube["lambda2"]) * nphi
+    Fq = torch.empty((nlos, nphi), dtype=torch.float32, device="cuda")
+    Fu = torch.empty_like(Fq)
+    res = {"phi_grid": f"the workload's grid, each phi moved by U(-0.2, 0.2) x {step:g} (seed 1810)",
+           "paths": {}}
+    for prec_name in ("bf16x3", "fp16x3", "fp32"):
+        prec = rs.PRECISIONS[prec_name]
+        pk = dict(idx=torch.empty(nlos, dtype=torch.int32, device="cuda"),
+                  phi_pk=torch.empty(nlos, device="cuda"), amp=torch.empty(nlos, device="cuda"),
+                  q_pk=torch.empty(nlos, device="cuda"), u_pk=torch.empty(nlos, device="cuda"))
+        n = steps if prec_name != "fp32" else max(2, steps // 2)
+        log(f"non-uniform grid: {prec_name}, {n} steps")
+        wall, ex, pkms = time_path(rs, plan, cube, prec, Fq, Fu, pk, n, 1, fused=False)
+        flop = MFMA_FLOP_PER_SAMPLE[prec_name] * samples
+        errs, _ = oracle_errors(cube2, sub, {prec_name: (Fq, Fu, pk["idx"])})
+        res["paths"][prec_name] = {
+            "step": "rmsynth_execute + rmsynth_peaks", "ms_per_step": wall, "transform_ms": ex,
+            "peaks_ms": pkms, "gsamples_s": samples / (wall * 1e-3) / 1e9,
+            "frac_of_peak": flop / (ex * 1e-3) / 1e12 / MFMA_PEAK_TFLOPS[prec_name],
+            "errors_vs_oracle": errs[prec_name]}
+        del pk
+    for p_ in ("bf16x3", "fp16x3"):
+        res["paths"][p_]["speedup_vs_fp32_step"] = (res["paths"]["fp32"]["ms_per_step"] /
+                                                     res["paths"][p_]["ms_per_step"])
+    plan.close()
+    del Fq, Fu
+    torch.cuda.empty_cache()
+    return res
+
+
 def rmclean_leg(rs, plan, Fq, Fu, lam, w, phi, sigma_f, src_los, steps):
     """RM-CLEAN (rmsynth_rmclean) of every LOS of the c3 spectrum (gain 0.1,
     cutoff 5 sigma_F, at most 1000 iterations), timed, and compared with the
@@ -768,6 +812,10 @@ def main():
         log("RM-CLEAN of the cube's F")
         res["rmclean"] = rmclean_leg(rs, plan, Fq, Fu, cube["lambda2"], cube["weights"], cube["phi"],
                                      noise_sigma_F(wl.sigma, cube["weights"]), cube["src_los"], 3)
+        if cube["layout"] == 0 and args.workload != "c4":
+            log("the cube on an irregular phi grid")
+            sub = stratified_subsample(nlos, cube["src_los"], 2048, seed=wl.seed + 13)
+            res["nonuniform_phi"] = nonuniform_leg(rs, cube, sub, 4)
     del Fq, Fu, pk, gpu_out, cube
     if fp32 is not None:
         del Fq2, Fu2, pk2

@@ -136,6 +136,10 @@ int rmsynth_rmsf(rmsynth_plan_t plan, float* R_re, float* R_im, void* stream);
  * outputs; other LOS are unaffected.  RMSYNTH_SPLIT_FP16 keeps a per-LOS
  * power-of-two scale in the workspace (any phi grid); the workspace is
  * overwritten, and calls that share one workspace must not overlap.
+ * The split precisions use factored phase tables on a uniform phi grid, a
+ * plan-time table of the whole split phase matrix on other grids when it
+ * holds at most 256 MiB (nchan x nphi up to about 1.6e7), and generate the
+ * phases per element beyond that; the results agree to the same bounds.
  * Errors: EINVAL (NULL buffers with nlos > 0, bad layout/precision, wrong
  * device current), EWORKSPACE, EHIP (launch failure).
  */
@@ -234,10 +238,11 @@ size_t rmsynth_search_noalloc_scratch_bytes(void);
  *   Cq, Cu   [nlos][nphi] device float: Re and Im of the components.
  *   Pq, Pu   [nlos][nchan] device float (LOS-major): Re and Im of P.
  *   precision  any rmsynth_precision.  The split precisions take tables
- *            instead of per-element phase generation when an axis is
- *            uniform: channels uniform in lambda^2 (the factored tables of
- *            the forward transform) or a uniform phi grid of at least 288
- *            values (K-tiles of 96 phi combined by Horner's rule).
+ *            instead of per-element phase generation: channels uniform in
+ *            lambda^2 (the factored tables of the forward transform), a
+ *            uniform phi grid of at least 288 values (K-tiles of 96 phi
+ *            combined by Horner's rule), otherwise the whole split phase
+ *            matrix when it holds at most 256 MiB.
  *   workspace  rmsynth_adjoint_workspace_size() bytes (0 except FP16), or
  *            less down to its value for 128 LOS (batches).
  * Every channel gets a value (weights do not enter).  A LOS with a

@@ -47,7 +47,8 @@ void free_plan(rmsynth_plan_s* p)
     void* bufs[] = {p->d_b, p->d_lambda2, p->d_w, p->d_phi, p->d_base, p->d_Tbf[0], p->d_Tbf[1],
                     p->d_Thf[0], p->d_Thf[1], p->d_nufft_rot, p->d_nufft_off, p->d_nufft_ent,
                     p->d_nufft_tw, p->d_nufft_deconv, p->d_kw, p->d_kbase, p->d_krot,
-                    p->d_Kbf[0], p->d_Kbf[1], p->d_Khf[0], p->d_Khf[1]};
+                    p->d_Kbf[0], p->d_Kbf[1], p->d_Khf[0], p->d_Khf[1], p->d_ew,
+                    p->d_Ebf[0], p->d_Ebf[1], p->d_Ehf[0], p->d_Ehf[1]};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     delete p;
@@ -88,6 +89,32 @@ int build_factor_tables(rmsynth_plan_s* p)
     (void)hipStreamDestroy(s);
     if (e != hipSuccess) return rms_hip_fail(e, "rmsynth_plan: phase-table kernel");
     if (e2 != hipSuccess) return rms_hip_fail(e2, "rmsynth_plan: phase-table kernel");
+    return RMSYNTH_OK;
+}
+
+// The explicit split phase table of a plan whose axes are not uniform (the
+// factored tables do not apply), when it fits kEtabMaxBytes; larger plans keep
+// the per-element phase generator.
+int build_etable(rmsynth_plan_s* p)
+{
+    const size_t nE = (size_t)(p->nchan_pad / 4) * p->nphi_pad;
+    if (nE * sizeof(uint4) * 4 > kEtabMaxBytes) return RMSYNTH_OK;
+    hipError_t e;
+    if ((e = hipMalloc(&p->d_ew, sizeof(float2) * p->nchan_pad)) != hipSuccess ||
+        (e = hipMalloc(&p->d_Ebf[0], sizeof(uint4) * nE)) != hipSuccess ||
+        (e = hipMalloc(&p->d_Ebf[1], sizeof(uint4) * nE)) != hipSuccess ||
+        (e = hipMalloc(&p->d_Ehf[0], sizeof(uint4) * nE)) != hipSuccess ||
+        (e = hipMalloc(&p->d_Ehf[1], sizeof(uint4) * nE)) != hipSuccess)
+        return rms_fail(RMSYNTH_ENOMEM, "rmsynth_plan: hipMalloc (phase table): %s", hipGetErrorString(e));
+    hipStream_t s = nullptr;
+    if ((e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) != hipSuccess)
+        return rms_hip_fail(e, "rmsynth_plan: hipStreamCreate");
+    e = launch_etable(*p, s);
+    hipError_t e2 = hipStreamSynchronize(s);
+    (void)hipStreamDestroy(s);
+    if (e != hipSuccess) return rms_hip_fail(e, "rmsynth_plan: phase-table kernel");
+    if (e2 != hipSuccess) return rms_hip_fail(e2, "rmsynth_plan: phase-table kernel");
+    p->etab = true;
     return RMSYNTH_OK;
 }
 
@@ -135,7 +162,7 @@ int build_adjoint_plan(rmsynth_plan_s* p, const double* lambda2, const double* p
     // now over every output lambda^2).
     double gmax = 0.0, phi0 = 0.0, dphi = 0.0;
     for (int32_t j = 0; j < p->nchan; ++j) gmax = std::max(gmax, std::fabs(hgrid[j]));
-    if (p->nphi < 3 * kKTile || !detect_uniform(phi, p->nphi, gmax, &phi0, &dphi)) return RMSYNTH_OK;
+    if (p->nphi < 3 * kKTile || !detect_uniform(phi, p->nphi, gmax, &phi0, &dphi)) return build_etable(q);
     q->cuniform = true;
     q->kb0 = phi0 / M_PI;
     q->kdb = dphi / M_PI;
@@ -263,6 +290,9 @@ int rmsynth_plan(const double* lambda2, const double* weights, int32_t nchan, co
             free_plan(p);
             return rc;
         }
+    } else if (int rc = build_etable(p)) {
+        free_plan(p);
+        return rc;
     }
     if (int rc = build_adjoint_plan(p, lambda2, phi)) {
         free_plan(p);
@@ -432,6 +462,7 @@ int run_execute(const rmsynth_plan_s* p, const float* Q, const float* U, int64_t
         else if (p->uniform) e = launch_synth_factored(*p, a, precision);
         else if (p->cuniform && layout == RMSYNTH_LOS_MAJOR && !parts && !recs)
             e = launch_synth_kfactored(*p, a, precision);
+        else if (p->etab && !parts && !recs) e = launch_synth_etable(*p, a, precision);
         else e = launch_synth_split(*p, a, precision);
         if (e != hipSuccess) return rms_hip_fail(e, who);
         b0 += m;

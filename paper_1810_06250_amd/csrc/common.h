@@ -56,6 +56,15 @@ struct rmsynth_plan_s {
     bool cuniform;
     double kb0, kdb;
     int32_t kpad;
+    // Explicit split phase table (synth_factored.hip, ET), present when
+    // neither axis is uniform and the table fits kEtabMaxBytes:
+    //   d_ew [nchan_pad] float2  (K w_j, 0)
+    //   d_E{bf,hf}[hi/lo] [nchan_pad/4][nphi_pad] uint4: 4 channels x (cos, sin)
+    //                   of 2 pi b_j phi_k, split into hi/lo
+    bool etab;
+    float2* d_ew;
+    uint4* d_Ebf[2];
+    uint4* d_Ehf[2];
     float2* d_kw;
     float2* d_kbase;
     float2* d_krot;
@@ -84,6 +93,7 @@ hipError_t launch_nufft(const rmsynth_plan_s& p, const float* Q, const float* U,
 
 constexpr int kFactorTile = 128;  // phi per tile of the factored kernels
 constexpr int kKTile = 96;        // channels per K-tile of the channel-factored form
+constexpr size_t kEtabMaxBytes = size_t(256) << 20;  // largest explicit phase table (4 arrays)
 
 constexpr int kChanPad = 32;    // channel padding granule (largest K-step)
 constexpr int kPhiPad = 256;    // phi padding granule (largest phi tile)
@@ -242,6 +252,8 @@ hipError_t launch_los_scale(const rmsynth_plan_s& p, const ExecArgs& a);
 hipError_t launch_factor_tables(const rmsynth_plan_s& p, hipStream_t s);
 hipError_t launch_kfactor_tables(const rmsynth_plan_s& p, hipStream_t s);
 hipError_t launch_synth_kfactored(const rmsynth_plan_s& p, const ExecArgs& a, int precision);
+hipError_t launch_etable(const rmsynth_plan_s& p, hipStream_t s);
+hipError_t launch_synth_etable(const rmsynth_plan_s& p, const ExecArgs& a, int precision);
 hipError_t launch_peaks(const rmsynth_plan_s& p, const float* Fq, const float* Fu, int64_t nlos,
                         int32_t* idx, float* phi_pk, float* amp, float* q_pk, float* u_pk,
                         hipStream_t s);

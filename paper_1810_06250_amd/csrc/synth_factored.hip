@@ -40,6 +40,11 @@
 // new K-tile (Horner's rule), K base_k in the epilogue; the data are only
 // weighted and split, not rotated.  KT is a multiple of three K-steps, so
 // every K-tile starts at the same point of the loop's register rotation.
+//
+// On a phi grid that is not uniform (and channels not uniform either) the
+// plan may hold the whole split phase matrix instead (ET: a plan-time table
+// of nchan x nphi entries, capped in size): the B tiles are then read from it
+// like the T tiles, and the data only weighted (K w_j), not rotated.
 #include <float.h>
 
 #include <type_traits>
@@ -111,10 +116,13 @@ __device__ __forceinline__ f32x16_t mfma16(uint4 a, uint4 b, f32x16_t c)
 // peak_merge_kernel, at part[half tile * part_ld + LOS].
 // PEAKS 2: F is not stored; the epilogue writes one PeakRec per (LOS, half
 // tile) instead, at rec[half tile * part_ld + LOS], for peak_merge_rec_kernel.
-// KF: the K-tile form above; base then holds (w_j, 0) per channel, Thi/Tlo
-// hold T' as [KT/4][ldT] quads, kbase and krot the K base_k and r_k per
-// output (LOS-major input, no peaks).
-template <int LAYOUT, bool FP16, bool FAST, bool FLAGS, int PEAKS, bool KF>
+// BM selects where the B tiles come from: 0 the tile-independent table T
+// with a per-tile rotation of the data (base [tile][channel]); 1 (KF) the
+// K-tile form above: base holds (w_j, 0) per channel, Thi/Tlo hold T' as
+// [KT/4][ldT] quads, kbase and krot the K base_k and r_k per output
+// (LOS-major input, no peaks); 2 (ET) the explicit phase table, [nchan/4][ldT]
+// quads, base holding (K w_j, 0) per channel (no peaks).
+template <int LAYOUT, bool FP16, bool FAST, bool FLAGS, int PEAKS, int BM>
 __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
     const float* __restrict__ Q, const float* __restrict__ U, int64_t nlos, int64_t ld,
     int nchan, const float2* __restrict__ base, const uint4* __restrict__ Thi,
@@ -124,7 +132,9 @@ __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
     PeakRec* __restrict__ rec, uint32_t neg_hi, const float2* __restrict__ kbase,
     const float2* __restrict__ krot, int ldT)
 {
+    constexpr bool KF = BM == 1, ET = BM == 2;
     static_assert(!KF || (PEAKS == 0 && LAYOUT == RMSYNTH_LOS_MAJOR), "KF: LOS-major, no peaks");
+    static_assert(!ET || PEAKS == 0, "ET: no peaks");
     // Triple-buffered A tiles (packed data) and T tiles (phase table), in one
     // block so that the epilogue can reuse all of it.
     struct Lds {
@@ -173,7 +183,7 @@ __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
         const int64_t g = l0 + rq + 32 * i;
         csc[i] = COAL && FP16 ? los_scale[g < nlos ? g : nlos - 1] : 1.0f;
     }
-    const_f4_ptr bt = (const_f4_ptr)(base + (KF ? 0 : (int64_t)tn * nchan_pad));
+    const_f4_ptr bt = (const_f4_ptr)(base + ((KF || ET) ? 0 : (int64_t)tn * nchan_pad));
     // KF: the K-step contracted at position k of the loop.  K-tile J covers
     // K-steps J KTS - pad .. (J + 1) KTS - pad - 1; the full K-tiles come
     // first, from the top down, then the valid K-steps of K-tile 0.
@@ -211,7 +221,11 @@ __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
     auto gload_vec = [&](Regs& R, int k) __attribute__((always_inline)) {
         const int ks = ks_of(k);
         const int j0 = ks * KC + 4 * hh;
-        if (!KF) {
+        if (ET) {
+            const int64_t at = (int64_t)(ks * NQ + (t >> 7)) * ldT + n0 + (t & 127);
+            R.th = Thi[at];
+            R.tl = Tlo[at];
+        } else if (!KF) {
             R.th = Thi[(int64_t)ks * (NQ * NT) + t];
             R.tl = Tlo[(int64_t)ks * (NQ * NT) + t];
         }
@@ -849,7 +863,7 @@ hipError_t launch_t(const rmsynth_plan_s& p, const ExecArgs& a)
     const bool full_k = p.nchan % KC == 0;
     const bool fast = full_k && (a.layout != RMSYNTH_LOS_MAJOR || a.vec4);
 #define RMS_LAUNCH(L, F, G, P)                                                                           \
-    hipLaunchKernelGGL((synth_factored_kernel<L, FP16, F, G, P, false>), dim3((unsigned)blocks), dim3(256), \
+    hipLaunchKernelGGL((synth_factored_kernel<L, FP16, F, G, P, 0>), dim3((unsigned)blocks), dim3(256),     \
                        0, a.stream, a.Q, a.U, a.nlos, a.ld, p.nchan, p.d_base, Thi, Tlo, p.nchan_pad, nk,  \
                        p.nphi, tiles_n, a.Fq, a.Fu, a.Fabs, a.los_scale, a.peak_part, a.peak_part_ld,      \
                        a.peak_rec, 0x80000000u, nullptr, nullptr, 0)
@@ -892,7 +906,7 @@ hipError_t launch_kf(const rmsynth_plan_s& p, const ExecArgs& a)
     // KF plans (adjoint plans) weight every channel 1: the flag-free forms.
     if (p.any_flagged) return hipErrorInvalidValue;
 #define RMS_LAUNCH_KF(F, G)                                                                              \
-    hipLaunchKernelGGL((synth_factored_kernel<RMSYNTH_LOS_MAJOR, FP16, F, G, 0, true>), dim3((unsigned)blocks), \
+    hipLaunchKernelGGL((synth_factored_kernel<RMSYNTH_LOS_MAJOR, FP16, F, G, 0, 1>), dim3((unsigned)blocks),  \
                        dim3(256), 0, a.stream, a.Q, a.U, a.nlos, a.ld, p.nchan, p.d_kw, Thi, Tlo,        \
                        p.nchan_pad, nk, p.nphi, tiles_n, a.Fq, a.Fu, a.Fabs, a.los_scale, nullptr,       \
                        (int64_t)0, nullptr, 0x80000000u, p.d_kbase, p.d_krot, p.nphi_pad)
@@ -940,7 +954,85 @@ __global__ void kfactor_tables_kernel(const double* __restrict__ g, const float*
     if (idx < nchan_pad) kw[idx] = make_float2(wj[idx], 0.0f);
 }
 
+// The explicit-table form (ET): any layout, F stored, no peaks.
+template <bool FP16>
+hipError_t launch_et(const rmsynth_plan_s& p, const ExecArgs& a)
+{
+    const int tiles_n = (p.nphi + NT - 1) / NT;
+    const int nk = (p.nchan + KC - 1) / KC;
+    const int64_t tiles_m = (a.nlos + MT - 1) / MT;
+    const int64_t blocks = tiles_m * tiles_n;
+    if (blocks <= 0) return hipSuccess;
+    const uint4* Thi = FP16 ? p.d_Ehf[0] : p.d_Ebf[0];
+    const uint4* Tlo = FP16 ? p.d_Ehf[1] : p.d_Ebf[1];
+    const bool fast = p.nchan % KC == 0 && (a.layout != RMSYNTH_LOS_MAJOR || a.vec4);
+#define RMS_LAUNCH_ET(L, F, G)                                                                           \
+    hipLaunchKernelGGL((synth_factored_kernel<L, FP16, F, G, 0, 2>), dim3((unsigned)blocks), dim3(256),  \
+                       0, a.stream, a.Q, a.U, a.nlos, a.ld, p.nchan, p.d_ew, Thi, Tlo, p.nchan_pad, nk,  \
+                       p.nphi, tiles_n, a.Fq, a.Fu, a.Fabs, a.los_scale, nullptr, (int64_t)0, nullptr,   \
+                       0x80000000u, nullptr, nullptr, p.nphi_pad)
+#define RMS_LAUNCH_ET_G(L, F)                      \
+    do {                                           \
+        if (p.any_flagged) RMS_LAUNCH_ET(L, F, true); \
+        else RMS_LAUNCH_ET(L, F, false);           \
+    } while (0)
+    if (a.layout == RMSYNTH_LOS_MAJOR) {
+        if (fast) RMS_LAUNCH_ET_G(RMSYNTH_LOS_MAJOR, true);
+        else RMS_LAUNCH_ET_G(RMSYNTH_LOS_MAJOR, false);
+    } else {
+        if (fast) RMS_LAUNCH_ET_G(RMSYNTH_FREQ_MAJOR, true);
+        else RMS_LAUNCH_ET_G(RMSYNTH_FREQ_MAJOR, false);
+    }
+#undef RMS_LAUNCH_ET_G
+#undef RMS_LAUNCH_ET
+    return hipGetLastError();
+}
+
+// The explicit phase table (FP64 argument reduction, FP32 sin/cos, as the
+// per-element generator): E[j/4][k] = 4 channels x (cos, sin)(2 pi b_j phi_k),
+// split; ew_j = (K w_j, 0).
+__global__ void etable_kernel(const double* __restrict__ bj, const double* __restrict__ phik,
+                              const float* __restrict__ wj, int nchan_pad, int nphi_pad, double K,
+                              float2* __restrict__ ew, uint4* __restrict__ bf_hi,
+                              uint4* __restrict__ bf_lo, uint4* __restrict__ hf_hi,
+                              uint4* __restrict__ hf_lo)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nE = (int64_t)(nchan_pad / 4) * nphi_pad;
+    if (idx < nE) {
+        const int quad = (int)(idx / nphi_pad), k = (int)(idx % nphi_pad);
+        uint32_t bh[4], bl[4], hh[4], hl[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            float c, sn;
+            phase_cos_sin(phik[k] * bj[4 * quad + e], c, sn);
+            split2_bf16(c, sn, bh[e], bl[e]);
+            split2_f16(c, sn, hh[e], hl[e]);
+        }
+        bf_hi[idx] = make_uint4(bh[0], bh[1], bh[2], bh[3]);
+        bf_lo[idx] = make_uint4(bl[0], bl[1], bl[2], bl[3]);
+        hf_hi[idx] = make_uint4(hh[0], hh[1], hh[2], hh[3]);
+        hf_lo[idx] = make_uint4(hl[0], hl[1], hl[2], hl[3]);
+    }
+    if (idx < nchan_pad) ew[idx] = make_float2((float)(K * (double)wj[idx]), 0.0f);
+}
+
 }  // namespace
+
+hipError_t launch_synth_etable(const rmsynth_plan_s& p, const ExecArgs& a, int precision)
+{
+    return precision == RMSYNTH_SPLIT_FP16 ? launch_et<true>(p, a) : launch_et<false>(p, a);
+}
+
+hipError_t launch_etable(const rmsynth_plan_s& p, hipStream_t stream)
+{
+    const int64_t nE = (int64_t)(p.nchan_pad / 4) * p.nphi_pad;
+    const int64_t n = std::max<int64_t>(nE, p.nchan_pad);
+    hipLaunchKernelGGL(etable_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, p.d_b,
+                       p.d_phi, p.d_w, p.nchan_pad, p.nphi_pad, p.K, p.d_ew, p.d_Ebf[0], p.d_Ebf[1],
+                       p.d_Ehf[0], p.d_Ehf[1]);
+    return hipGetLastError();
+}
 
 hipError_t launch_synth_kfactored(const rmsynth_plan_s& p, const ExecArgs& a, int precision)
 {
@@ -959,9 +1051,10 @@ hipError_t launch_kfactor_tables(const rmsynth_plan_s& p, hipStream_t stream)
 
 hipError_t launch_los_scale(const rmsynth_plan_s& p, const ExecArgs& a)
 {
-    // The factored kernels fold K into the data they split; the per-element
-    // split kernel applies it in the epilogue, so its scale ignores K.
-    const float k = p.uniform ? (float)p.K : 1.0f;
+    // The factored and explicit-table kernels fold K into the data they
+    // split; the per-element split kernel applies it in the epilogue, so its
+    // scale ignores K (K = 1 in the channel-factored adjoint plans).
+    const float k = (p.uniform || p.etab) ? (float)p.K : 1.0f;
     if (a.layout == RMSYNTH_LOS_MAJOR)
         hipLaunchKernelGGL(los_scale_kernel<RMSYNTH_LOS_MAJOR>, dim3((unsigned)((a.nlos + 3) / 4)),
                            dim3(256), 0, a.stream, a.Q, a.U, a.nlos, a.ld, p.nchan, p.d_w, k,

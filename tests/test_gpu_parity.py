@@ -398,6 +398,24 @@ def test_nonuniform_phi_grid(prec, layout):
            phi, layout, PREC_TOL[prec])
 
 
+@pytest.mark.parametrize("prec", ["bf16x3", "fp16x3"])
+def test_irregular_grid_above_the_table_cap(prec):
+    """An irregular grid whose plan-time phase table would pass its size cap
+    (4096 channels x 4200 phi) keeps the per-element phase generator; both
+    forms agree with the oracle."""
+    note(f"irregular grid above the table cap, {prec}")
+    rng = np.random.default_rng(91)
+    lam = band_lambda2(110.0, 190.0, 4096)
+    w = np.ones(lam.size)
+    phi = np.sort(rng.uniform(-400, 400, 4200))
+    plan = rs.Plan(lam, w, phi)
+    nlos = 48
+    Q = np.float32(rng.standard_normal((nlos, lam.size)) * 1e-2)
+    U = np.float32(rng.standard_normal((nlos, lam.size)) * 1e-2)
+    out = _run(plan, dev32(Q), dev32(U), LOS_MAJOR, PRECS[prec])
+    _check(out, Q.astype(np.float64), U.astype(np.float64), lam, w, phi, LOS_MAJOR, PREC_TOL[prec])
+
+
 def test_fp16_split_needs_its_workspace():
     """The FP16 split keeps a per-LOS scale in the caller's workspace, on
     uniform and irregular phi grids alike."""
