@@ -153,7 +153,8 @@ int rmsynth_execute(rmsynth_plan_t plan, const float* Q, const float* U, int64_t
  * outputs, in one call: arguments as there (Fq, Fu are written as by
  * rmsynth_execute; idx, phi_pk, amp, q_pk, u_pk as by rmsynth_peaks, idx
  * required, the others may be NULL).  With a split precision on a uniform phi
- * grid the transform kernels reduce |F|^2 per (LOS, phi tile) while the tile
+ * grid, or on an irregular one whose phase table the plan holds (see
+ * rmsynth_execute), the transform kernels reduce |F|^2 per (LOS, phi tile) while the tile
  * is still in registers and a small kernel merges the tiles, so the outputs are
  * not read back; the results are identical to the two separate calls.
  *   workspace: rmsynth_execute_peaks_workspace_size() bytes (the FP16
@@ -186,9 +187,10 @@ int rmsynth_execute_peaks_workspace_size(rmsynth_plan_t plan, int64_t nlos, int3
  *            rmsynth_peak_fit (bit-identical to it on the stored F).
  *   workspace: rmsynth_search_workspace_size() bytes, or less down to its
  *            value for 128 LOS (LOS batches).  With a split precision on a
- *            uniform phi grid the transform kernels reduce each (LOS, 64 phi)
- *            to a 32-byte record while F is in registers (32 bytes per LOS and
- *            64 phi); other paths hold F of one batch in the workspace.
+ *            uniform phi grid, or on an irregular one whose phase table the
+ *            plan holds, the transform kernels reduce each (LOS, 64 phi) to a
+ *            32-byte record while F is in registers (32 bytes per LOS and 64
+ *            phi); other paths hold F of one batch in the workspace.
  * Errors as rmsynth_execute.
  */
 int rmsynth_search(rmsynth_plan_t plan, const float* Q, const float* U, int64_t nlos,
@@ -215,7 +217,7 @@ int rmsynth_search_workspace_size(rmsynth_plan_t plan, int64_t nlos, int32_t lay
  *   the caller.  No part of the array has to start at zero.
  * Errors as rmsynth_search; EINVAL when one batch of 128 LOS does not fit
  * the array (only the unfused paths, which hold F of a batch: nphi above
- * 65536 on a non-uniform grid or at FP32).
+ * 65536 at FP32, or on an irregular grid too large for a phase table).
  */
 int rmsynth_search_noalloc(rmsynth_plan_t plan, const float* Q, const float* U, int64_t nlos,
                            int32_t layout, int32_t precision, int32_t* idx, float* phi_pk,

@@ -115,6 +115,7 @@ int build_etable(rmsynth_plan_s* p)
     if (e != hipSuccess) return rms_hip_fail(e, "rmsynth_plan: phase-table kernel");
     if (e2 != hipSuccess) return rms_hip_fail(e2, "rmsynth_plan: phase-table kernel");
     p->etab = true;
+    p->ftiles = (int32_t)((p->nphi + kFactorTile - 1) / kFactorTile);  // peak records per LOS: 2 ftiles
     return RMSYNTH_OK;
 }
 
@@ -347,7 +348,7 @@ size_t scale_bytes(int64_t nlos) { return region(nlos, 4); }
 
 bool fused_peaks(const rmsynth_plan_s* p, int32_t precision)
 {
-    return precision != RMSYNTH_FP32 && p->uniform;
+    return precision != RMSYNTH_FP32 && (p->uniform || p->etab);
 }
 
 int check_execute_args(const rmsynth_plan_s* p, int64_t nlos, int32_t layout, int32_t precision,
@@ -462,7 +463,7 @@ int run_execute(const rmsynth_plan_s* p, const float* Q, const float* U, int64_t
         else if (p->uniform) e = launch_synth_factored(*p, a, precision);
         else if (p->cuniform && layout == RMSYNTH_LOS_MAJOR && !parts && !recs)
             e = launch_synth_kfactored(*p, a, precision);
-        else if (p->etab && !parts && !recs) e = launch_synth_etable(*p, a, precision);
+        else if (p->etab) e = launch_synth_etable(*p, a, precision);
         else e = launch_synth_split(*p, a, precision);
         if (e != hipSuccess) return rms_hip_fail(e, who);
         b0 += m;

@@ -121,7 +121,7 @@ __device__ __forceinline__ f32x16_t mfma16(uint4 a, uint4 b, f32x16_t c)
 // K-tile form above: base holds (w_j, 0) per channel, Thi/Tlo hold T' as
 // [KT/4][ldT] quads, kbase and krot the K base_k and r_k per output
 // (LOS-major input, no peaks); 2 (ET) the explicit phase table, [nchan/4][ldT]
-// quads, base holding (K w_j, 0) per channel (no peaks).
+// quads, base holding (K w_j, 0) per channel.
 template <int LAYOUT, bool FP16, bool FAST, bool FLAGS, int PEAKS, int BM>
 __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
     const float* __restrict__ Q, const float* __restrict__ U, int64_t nlos, int64_t ld,
@@ -134,7 +134,6 @@ __global__ __launch_bounds__(256, 2) void synth_factored_kernel(
 {
     constexpr bool KF = BM == 1, ET = BM == 2;
     static_assert(!KF || (PEAKS == 0 && LAYOUT == RMSYNTH_LOS_MAJOR), "KF: LOS-major, no peaks");
-    static_assert(!ET || PEAKS == 0, "ET: no peaks");
     // Triple-buffered A tiles (packed data) and T tiles (phase table), in one
     // block so that the epilogue can reuse all of it.
     struct Lds {
@@ -954,7 +953,7 @@ __global__ void kfactor_tables_kernel(const double* __restrict__ g, const float*
     if (idx < nchan_pad) kw[idx] = make_float2(wj[idx], 0.0f);
 }
 
-// The explicit-table form (ET): any layout, F stored, no peaks.
+// The explicit-table form (ET): any layout, with or without the fused peaks.
 template <bool FP16>
 hipError_t launch_et(const rmsynth_plan_s& p, const ExecArgs& a)
 {
@@ -966,15 +965,21 @@ hipError_t launch_et(const rmsynth_plan_s& p, const ExecArgs& a)
     const uint4* Thi = FP16 ? p.d_Ehf[0] : p.d_Ebf[0];
     const uint4* Tlo = FP16 ? p.d_Ehf[1] : p.d_Ebf[1];
     const bool fast = p.nchan % KC == 0 && (a.layout != RMSYNTH_LOS_MAJOR || a.vec4);
-#define RMS_LAUNCH_ET(L, F, G)                                                                           \
-    hipLaunchKernelGGL((synth_factored_kernel<L, FP16, F, G, 0, 2>), dim3((unsigned)blocks), dim3(256),  \
+#define RMS_LAUNCH_ET(L, F, G, P)                                                                        \
+    hipLaunchKernelGGL((synth_factored_kernel<L, FP16, F, G, P, 2>), dim3((unsigned)blocks), dim3(256),  \
                        0, a.stream, a.Q, a.U, a.nlos, a.ld, p.nchan, p.d_ew, Thi, Tlo, p.nchan_pad, nk,  \
-                       p.nphi, tiles_n, a.Fq, a.Fu, a.Fabs, a.los_scale, nullptr, (int64_t)0, nullptr,   \
-                       0x80000000u, nullptr, nullptr, p.nphi_pad)
-#define RMS_LAUNCH_ET_G(L, F)                      \
-    do {                                           \
-        if (p.any_flagged) RMS_LAUNCH_ET(L, F, true); \
-        else RMS_LAUNCH_ET(L, F, false);           \
+                       p.nphi, tiles_n, a.Fq, a.Fu, a.Fabs, a.los_scale, a.peak_part, a.peak_part_ld,    \
+                       a.peak_rec, 0x80000000u, nullptr, nullptr, p.nphi_pad)
+#define RMS_LAUNCH_ET_P(L, F, G)                      \
+    do {                                              \
+        if (a.peak_rec) RMS_LAUNCH_ET(L, F, G, 2);    \
+        else if (a.peak_part) RMS_LAUNCH_ET(L, F, G, 1); \
+        else RMS_LAUNCH_ET(L, F, G, 0);               \
+    } while (0)
+#define RMS_LAUNCH_ET_G(L, F)                            \
+    do {                                                 \
+        if (p.any_flagged) RMS_LAUNCH_ET_P(L, F, true);  \
+        else RMS_LAUNCH_ET_P(L, F, false);               \
     } while (0)
     if (a.layout == RMSYNTH_LOS_MAJOR) {
         if (fast) RMS_LAUNCH_ET_G(RMSYNTH_LOS_MAJOR, true);
@@ -984,6 +989,7 @@ hipError_t launch_et(const rmsynth_plan_s& p, const ExecArgs& a)
         else RMS_LAUNCH_ET_G(RMSYNTH_FREQ_MAJOR, false);
     }
 #undef RMS_LAUNCH_ET_G
+#undef RMS_LAUNCH_ET_P
 #undef RMS_LAUNCH_ET
     return hipGetLastError();
 }

@@ -490,6 +490,23 @@ def test_execute_peaks_equals_execute_then_peaks(prec, layout, nlos, nchan, nphi
 
 
 @pytest.mark.parametrize("prec", ["bf16x3", "fp16x3"])
+@pytest.mark.parametrize("layout", [LOS_MAJOR, FREQ_MAJOR], ids=["los", "freq"])
+def test_execute_peaks_on_an_irregular_grid(prec, layout):
+    """The fused peaks on the plan-time phase table (irregular grid): bit for
+    bit execute + peaks, ragged tiles, flagged channels, a non-finite LOS."""
+    note(f"execute_peaks irregular {prec} layout={layout}")
+    c = make_small_cube(300, 72, 10, seed=44, nflag=5, nsrc=12)
+    Q, U = np.float32(c["Q"]), np.float32(c["U"])
+    Q[3, int(np.flatnonzero(c["weights"] > 0)[0])] = np.nan
+    phi = np.sort(np.random.default_rng(45).uniform(-200, 200, 333))
+    plan = rs.Plan(c["lambda2"], c["weights"], phi)
+    if layout == FREQ_MAJOR:
+        Q, U = np.ascontiguousarray(Q.T), np.ascontiguousarray(U.T)
+    idx = _compare_fused(plan, dev32(Q), dev32(U), layout, prec)
+    assert idx[3] == -1
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp16x3"])
 def test_execute_peaks_all_ties_take_the_first_phi(prec):
     """A zero cube: every |F| is 0, so every phi ties and the peak is phi_0."""
     c = make_small_cube(300, 40, 700, seed=9)
