@@ -67,7 +67,7 @@ def paper_context():
 KERNEL_SRC = [os.path.join(ROOT, "paper_1810_06250_amd", "csrc", f)
               for f in ("synth_factored.hip", "common.h")]
 TRAFFIC = {
-    ("c3", "bf16x3", "bad4bffb574e7b5e"): 2.0 * 2389781.5 * 1024 + 1.0 * 16985156.5 * 1024,
+    ("c3", "bf16x3", "c091c886c2c0df0f"): 2.0 * 2395509.8 * 1024 + 1.0 * 17044737.2 * 1024,
 }
 
 
@@ -439,10 +439,11 @@ def nufft_leg(rs, plan, cube, sub, steps):
 
 def nonuniform_leg(rs, cube, sub, steps):
     """The same cube on an irregular phi grid (each phi of the workload moved by
-    up to +-0.2 of its step, seeded): the split precisions then generate the
-    phase tiles per element (synth_split_kernel), FP32 as before.  One step =
-    rmsynth_execute + rmsynth_peaks; errors against the FP64 oracle on the
-    stratified subsample."""
+    up to +-0.2 of its step, seeded): the split precisions then read the
+    plan's phase table (with the fused peaks: one rmsynth_execute_peaks per
+    step), FP32 generates the phases per element (rmsynth_execute +
+    rmsynth_peaks).  Errors against the FP64 oracle on the stratified
+    subsample."""
     import torch
     phi = np.asarray(cube["phi"], dtype=np.float64)
     step = float(phi[1] - phi[0])
@@ -463,11 +464,13 @@ def nonuniform_leg(rs, cube, sub, steps):
                   q_pk=torch.empty(nlos, device="cuda"), u_pk=torch.empty(nlos, device="cuda"))
         n = steps if prec_name != "fp32" else max(2, steps // 2)
         log(f"non-uniform grid: {prec_name}, {n} steps")
-        wall, ex, pkms = time_path(rs, plan, cube, prec, Fq, Fu, pk, n, 1, fused=False)
+        fused = prec_name != "fp32"
+        wall, ex, pkms = time_path(rs, plan, cube, prec, Fq, Fu, pk, n, 1, fused=fused)
         flop = MFMA_FLOP_PER_SAMPLE[prec_name] * samples
         errs, _ = oracle_errors(cube2, sub, {prec_name: (Fq, Fu, pk["idx"])})
         res["paths"][prec_name] = {
-            "step": "rmsynth_execute + rmsynth_peaks", "ms_per_step": wall, "transform_ms": ex,
+            "step": "rmsynth_execute_peaks" if fused else "rmsynth_execute + rmsynth_peaks",
+            "ms_per_step": wall, "transform_ms": ex,
             "peaks_ms": pkms, "gsamples_s": samples / (wall * 1e-3) / 1e9,
             "frac_of_peak": flop / (ex * 1e-3) / 1e12 / MFMA_PEAK_TFLOPS[prec_name],
             "errors_vs_oracle": errs[prec_name]}
