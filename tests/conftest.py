@@ -18,3 +18,17 @@ def oracle_mod():
     if not os.path.exists(oracle.lib_path()):
         oracle.build(force=False)
     return oracle
+
+
+@pytest.fixture(autouse=True, scope="module")
+def _release_device_cache():
+    """The full-size tests hold most of the card; return the blocks torch's
+    caching allocator keeps after each module so that the next module starts
+    from an empty device (nothing is initialised on a CPU-only run)."""
+    yield
+    if "torch" in sys.modules:
+        import gc
+        import torch
+        if torch.cuda.is_initialized():
+            gc.collect()
+            torch.cuda.empty_cache()

@@ -354,7 +354,14 @@ def _full_size(name, prec_list, nsub):
         note(f"{name} {prec}: sub-grid peak max |dphi| {d.max():.2e} rad/m^2 (bar {bp[same].max():.2e})")
         assert np.all(d <= bp[same] + 2.0 ** -23 * np.abs(rfit[0][same]))
         note(f"{name}: search {prec}")
-        s = plan.search(cube["Q"], cube["U"], cube["layout"], PRECS[prec])
+        # The unfused (FP32) search holds F of a batch in its workspace: cap it
+        # at 16 GiB (LOS batches, same results), which keeps c4 (134 GB of F
+        # already resident) within the card.
+        least = rs.rmsynth_search_workspace_size(plan.handle, 128, cube["layout"], PRECS[prec])
+        whole = rs.rmsynth_search_workspace_size(plan.handle, wl.nlos, cube["layout"], PRECS[prec])
+        torch.cuda.empty_cache()
+        s = plan.search(cube["Q"], cube["U"], cube["layout"], PRECS[prec],
+                        workspace_bytes=min(whole, max(least, 16 << 30)))
         for key in ("idx", "amp", "q_pk", "u_pk"):
             assert torch.equal(s[key], pk[key]), (name, prec, "search", key)
         assert torch.equal(s["phi_fit"], pf) and torch.equal(s["amp_fit"], af)
