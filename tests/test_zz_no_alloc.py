@@ -1,8 +1,9 @@
 """rmsynth_search_noalloc (the search with its workspace in the library's own
 fixed device array) against rmsynth_search with a caller's workspace, through
 the C ABI: two calls in a row on one device, the second with a smaller input,
-for the fused split path (records in the array, several batches) and the FP32
-path (F of a batch in the array)."""
+for the fused split path (records in the array, several batches) on a
+uniform and on an irregular phi grid, and the FP32 path (F of a batch in the
+array)."""
 import numpy as np
 import pytest
 
@@ -36,19 +37,24 @@ def _noalloc(plan, Q, U, n, layout, prec):
     return out
 
 
-@pytest.mark.parametrize("prec,layout,nlos,nchan,nphi", [
-    (rs.RMSYNTH_SPLIT_BF16, LOS_MAJOR, 150_000, 64, 2001),
-    (rs.RMSYNTH_SPLIT_FP16, FREQ_MAJOR, 70_000, 40, 4001),
-    (rs.RMSYNTH_FP32, LOS_MAJOR, 20_000, 48, 1501),
+@pytest.mark.parametrize("prec,layout,nlos,nchan,nphi,irregular", [
+    (rs.RMSYNTH_SPLIT_BF16, LOS_MAJOR, 150_000, 64, 2001, False),
+    (rs.RMSYNTH_SPLIT_FP16, FREQ_MAJOR, 70_000, 40, 4001, False),
+    (rs.RMSYNTH_SPLIT_BF16, LOS_MAJOR, 120_000, 56, 1601, True),
+    (rs.RMSYNTH_FP32, LOS_MAJOR, 20_000, 48, 1501, False),
 ])
-def test_noalloc_search_equals_search(prec, layout, nlos, nchan, nphi):
+def test_noalloc_search_equals_search(prec, layout, nlos, nchan, nphi, irregular):
     import torch
     scratch = rs.rmsynth_search_noalloc_scratch_bytes()
     assert scratch == 64 << 20
     for call, n in enumerate((nlos, nlos // 7 + 3)):
         note(f"noalloc prec={prec} layout={layout} call {call}: {n} LOS x {nchan} x {nphi}")
         c = make_small_cube(n, nchan, nphi, seed=100 * call + prec, nflag=3, nsrc=n // 50)
-        plan = rs.Plan(c["lambda2"], c["weights"], c["phi"])
+        phi = c["phi"]
+        if irregular:       # each phi moved by up to a fifth of the step: still sorted
+            step = phi[1] - phi[0]
+            phi = phi + np.random.default_rng(call).uniform(-0.2, 0.2, phi.size) * step
+        plan = rs.Plan(c["lambda2"], c["weights"], phi)
         Q, U = np.float32(c["Q"]), np.float32(c["U"])
         Q[5, int(np.flatnonzero(c["weights"] > 0)[0])] = np.nan
         if layout == FREQ_MAJOR:
