@@ -17,6 +17,8 @@
 
 namespace {
 
+typedef _Float16 f16x4_t __attribute__((ext_vector_type(4)));
+
 // FP32 to half, the FP32 value rounded first: the empty asm keeps the
 // compiler from fusing the multiply or add that produced x and the
 // conversion into one mixed-precision FMA (a single rounding from the exact
@@ -629,14 +631,17 @@ __global__ __launch_bounds__(256, 3) void infer_fused_kernel(
 
 // One-pass inference for nchan = 2 PER (PER a multiple of 16), hidden widths
 // 256/256, 16-byte aligned rows.  One workgroup per 64 LOS, two per CU.  The
-// four threads of a row each load one contiguous quarter of [Q | U] (PER
-// floats, all loads in flight at once), so the block is read from HBM once;
-// the row's sum of squares follows from two shuffles, and the normalised
-// halves go to an LDS tile holding the whole 64 x 2 nchan input.  Layer 1
-// then runs over all K-chunks with no barrier and no further input loads
-// (only the weight fragments, two chunks ahead); h1 reuses the tile's LDS;
-// layer 2 and the head are those of infer_fused_kernel.  Rounding points
-// and outputs per LOS do not depend on the LOS's position in the batch.
+// block is read from HBM once, every load in flight at once: sixteen lanes
+// share a row, lane k reading float4 number k + 16 p of [Q | U], so each load
+// instruction covers 256 contiguous bytes of four rows (a quarter of a row
+// per thread touched one cache line per lane and was 11 % slower).  The row's
+// sum of squares takes four shuffles, and the normalised halves go to an LDS
+// tile holding the whole 64 x 2 nchan input.  Layer 1 then runs over all
+// K-chunks with no barrier and no further input loads (only the weight
+// fragments, two chunks ahead); h1 reuses the tile's LDS; layer 2 and the
+// head are those of infer_fused_kernel, except that the head's sums over the
+// 32 lanes of a half-wave transpose as they go (below).  Rounding points and
+// outputs per LOS do not depend on the LOS's position in the batch.
 template <int PER, bool UNITW>
 __global__ __launch_bounds__(256, 2) void infer_onepass_kernel(
     const float* __restrict__ Q, const float* __restrict__ U, int64_t nlos,
@@ -656,40 +661,55 @@ __global__ __launch_bounds__(256, 2) void infer_onepass_kernel(
     const int t = threadIdx.x, lane = t & 63;
     const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
     const int64_t r0 = (int64_t)blockIdx.x * FR;
-    const int lrow = t >> 2, qq = t & 3;
-    // Rows past the end read the last LOS (in bounds); their outputs are never stored.
-    const int64_t ll = r0 + lrow < nlos ? r0 + lrow : nlos - 1;
     {
-        const float* src = (qq < 2 ? Q : U) + ll * nchan + (qq & 1) * PER;
-        const float* wq = w + (qq & 1) * PER;
+        // Wave wv holds rows 16 wv + 4 m + g (m = 0..3, g = lane >> 4); lane
+        // k = lane & 15 holds float4 number f = k + 16 p (p < NP) of the row's
+        // [Q | U], whose four values are x columns 4 f .. 4 f + 3.
+        constexpr int NQ = nchan / 4, NP = nin / 64;
+        const int g = lane >> 4, k = lane & 15;
         float v[PER];
 #pragma unroll
-        for (int i = 0; i < PER / 4; ++i) {
-            const float4 a = reinterpret_cast<const float4*>(src)[i];
-            v[4 * i] = a.x; v[4 * i + 1] = a.y; v[4 * i + 2] = a.z; v[4 * i + 3] = a.w;
-        }
-        float ss = 0.0f;
+        for (int m = 0; m < 4; ++m) {
+            // Rows past the end read the last LOS (in bounds); their outputs are never stored.
+            const int64_t rr = r0 + 16 * wave + 4 * m + g;
+            const int64_t ll = rr < nlos ? rr : nlos - 1;
 #pragma unroll
-        for (int i = 0; i < PER / 4; ++i) {
-            const float4 wv = UNITW ? make_float4(1.0f, 1.0f, 1.0f, 1.0f)
-                                    : reinterpret_cast<const float4*>(wq)[i];
-            const float ww[4] = {wv.x, wv.y, wv.z, wv.w};
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const float a = ww[e] == 0.0f ? 0.0f : ww[e] * v[4 * i + e];
-                v[4 * i + e] = a;
-                ss = __builtin_fmaf(a, a, ss);
+            for (int p = 0; p < NP; ++p) {
+                const int f = k + 16 * p;
+                const float* row = (f < NQ ? Q : U) + ll * nchan;
+                const float4 a = reinterpret_cast<const float4*>(row)[f < NQ ? f : f - NQ];
+                float* d = &v[4 * (m * NP + p)];
+                d[0] = a.x; d[1] = a.y; d[2] = a.z; d[3] = a.w;
             }
         }
-        ss += __shfl_xor(ss, 1, 64);
-        ss += __shfl_xor(ss, 2, 64);
-        const float inv = ss > 0.0f ? 1.0f / sqrtf(ss / (float)nin) : (ss == 0.0f ? 0.0f : ss);
 #pragma unroll
-        for (int i = 0; i < PER / 8; ++i) {
-            f16x8_t xv;
+        for (int m = 0; m < 4; ++m) {
+            float ss = 0.0f;
 #pragma unroll
-            for (int e = 0; e < 8; ++e) xv[e] = half_of(v[8 * i + e] * inv);
-            *reinterpret_cast<f16x8_t*>(&sx[lrow][qq * PER + 8 * i]) = xv;
+            for (int p = 0; p < NP; ++p) {
+                const int f = k + 16 * p;
+                const float4 wv = UNITW ? make_float4(1.0f, 1.0f, 1.0f, 1.0f)
+                                        : reinterpret_cast<const float4*>(w)[f < NQ ? f : f - NQ];
+                const float ww[4] = {wv.x, wv.y, wv.z, wv.w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    float& x = v[4 * (m * NP + p) + e];
+                    const float a = ww[e] == 0.0f ? 0.0f : ww[e] * x;
+                    x = a;
+                    ss = __builtin_fmaf(a, a, ss);
+                }
+            }
+#pragma unroll
+            for (int off = 1; off < 16; off <<= 1) ss += __shfl_xor(ss, off, 64);
+            const float inv = ss > 0.0f ? 1.0f / sqrtf(ss / (float)nin) : (ss == 0.0f ? 0.0f : ss);
+            const int row = 16 * wave + 4 * m + g;
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                f16x4_t xv;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) xv[e] = half_of(v[4 * (m * NP + p) + e] * inv);
+                *reinterpret_cast<f16x4_t*>(&sx[row][4 * (k + 16 * p)]) = xv;
+            }
         }
     }
     __syncthreads();
@@ -792,22 +812,50 @@ __global__ __launch_bounds__(256, 2) void infer_onepass_kernel(
                 p1[rb][v] = __builtin_fmaf(h, w1, p1[rb][v]);
             }
     }
+    // Each row's sum over the 32 lanes of its half-wave adds the pairs
+    // (r, r ^ o) for o = 16, 8, 4, 2, 1.  At 256 or 288 channels the lanes
+    // transpose as they add: at offset o a lane keeps the half of its 32 row
+    // sums that bit o of its lane number selects and adds the partner's copy
+    // of that half, so the five steps take 31 shuffles per output instead of
+    // 160 and leave row q = r in lane r; the tree, and so every sum, is the
+    // one of the plain butterfly (which the 128-channel form keeps: there it
+    // measured faster).
+    if constexpr (PER >= 128) {
+        float a0[32], a1[32];
 #pragma unroll
-    for (int rb = 0; rb < 2; ++rb)
+        for (int q = 0; q < 32; ++q) { a0[q] = p0[q >> 4][q & 15]; a1[q] = p1[q >> 4][q & 15]; }
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            float a = p0[rb][v], b = p1[rb][v];
+        for (int o = 16; o > 0; o >>= 1) {   // a lane holds 2 o row sums before this step
+            const bool hi = (r & o) != 0;
 #pragma unroll
-            for (int off = 16; off > 0; off >>= 1) {
-                a += __shfl_xor(a, off, 64);
-                b += __shfl_xor(b, off, 64);
-            }
-            if (r == 0) {
-                const int m = 32 * rb + 8 * (v >> 2) + 4 * hsel + (v & 3);
-                part[wave][m][0] = a;
-                part[wave][m][1] = b;
+            for (int j = 0; j < o; ++j) {
+                const float k0 = hi ? a0[j + o] : a0[j], s0 = hi ? a0[j] : a0[j + o];
+                const float k1 = hi ? a1[j + o] : a1[j], s1 = hi ? a1[j] : a1[j + o];
+                a0[j] = k0 + __shfl_xor(s0, o, 64);
+                a1[j] = k1 + __shfl_xor(s1, o, 64);
             }
         }
+        const int m = 32 * (r >> 4) + 8 * ((r & 15) >> 2) + 4 * hsel + (r & 3);
+        part[wave][m][0] = a0[0];
+        part[wave][m][1] = a1[0];
+    } else {
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                float a = p0[rb][v], b = p1[rb][v];
+#pragma unroll
+                for (int off = 16; off > 0; off >>= 1) {
+                    a += __shfl_xor(a, off, 64);
+                    b += __shfl_xor(b, off, 64);
+                }
+                if (r == 0) {
+                    const int m = 32 * rb + 8 * (v >> 2) + 4 * hsel + (v & 3);
+                    part[wave][m][0] = a;
+                    part[wave][m][1] = b;
+                }
+            }
+    }
     __syncthreads();
     if (t < FR && r0 + t < nlos) {
         const float o0 = ((part[0][t][0] + part[1][t][0]) + (part[2][t][0] + part[3][t][0])) + b3[0];

@@ -175,10 +175,13 @@ def test_adam_steps_match_oracle():
     np.testing.assert_array_equal(W1[:, off], _blocks(p32, 2 * nchan, h1, h2)[0][:, off])
 
 
-@pytest.mark.parametrize("nchan,h1,h2", [(96, 128, 64), (288, 256, 256), (33, 256, 256)])
+@pytest.mark.parametrize("nchan,h1,h2", [(96, 128, 64), (288, 256, 256), (256, 256, 256),
+                                         (128, 256, 256), (33, 256, 256)])
 def test_infer_matches_oracle_and_is_chunk_invariant(nchan, h1, h2):
     """(96, 128, 64) runs the layer-by-layer path in 65 536-row chunks; the
-    256 x 256 shapes run the fused one-pass kernel (33 channels: ragged K)."""
+    256 x 256 shapes run the fused kernels: the one-pass kernel for 288, 256
+    and 128 channels (the head's transposing sums at 288 and 256, the plain
+    butterfly at 128), the two-pass one for 33 channels (ragged K)."""
     n = 70_000                      # crosses the 65 536-row inference chunk
     note(f"mlp infer n={n} nchan={nchan} h1={h1} h2={h2}")
     w, Q, U, phi, det, p32 = _case(5, n, nchan, h1, h2)
