@@ -200,6 +200,47 @@ def test_infer_matches_oracle_and_is_chunk_invariant(nchan, h1, h2):
     np.testing.assert_array_equal(host(sc2), sc[65_400:65_700])
 
 
+@pytest.mark.parametrize("nchan", [288, 256, 128])
+def test_onepass_small_batches_and_nonfinite_rows(nchan):
+    """The one-pass kernel on batches of 1, 63 and 65 rows (rows past the end
+    of a batch read its last LOS and are never stored) reproduces those rows
+    of a larger batch bit for bit.  A non-finite value in an unflagged channel
+    makes its row NaN; one in a flagged channel is ignored (the row equals
+    the row with that value zeroed); an all-zero row stays finite."""
+    h1 = h2 = 256
+    n = 200
+    w, Q, U, _, _, p32 = _case(41 + nchan, n, nchan, h1, h2)
+    flagged, kept = np.flatnonzero(w == 0), np.flatnonzero(w > 0)
+    assert flagged.size and kept.size
+    Q[7, flagged[0]] = np.nan
+    U[9, kept[0]] = np.inf
+    Q[11] = 0.0
+    U[11] = 0.0
+    net = rs.Mlp(nchan, h1, h2, weights=w, phi_scale=PHI_SCALE)
+    net.set_params(p32)
+    Qd, Ud = dev32(Q), dev32(U)
+    ph, sc = (host(t) for t in net.infer(Qd, Ud))
+    assert np.isnan(ph[9]) and np.isnan(sc[9])
+    finite = np.ones(n, bool)
+    finite[9] = False
+    assert np.all(np.isfinite(ph[finite])) and np.all(np.isfinite(sc[finite]))
+    Q7 = Q[7:8].copy()
+    Q7[0, flagged[0]] = 0.0
+    p7, s7 = (host(t) for t in net.infer(dev32(Q7), Ud[7:8].contiguous()))
+    np.testing.assert_array_equal(p7, ph[7:8])
+    np.testing.assert_array_equal(s7, sc[7:8])
+    ok = finite.copy()
+    ok[7] = False
+    params = _blocks(p32.astype(np.float64), 2 * nchan, h1, h2)
+    x = omlp.normalise(Q[ok].astype(np.float64), U[ok].astype(np.float64), w)
+    _check_outputs(ph[ok], sc[ok], params, x)
+    for a, m in ((0, 1), (7, 63), (120, 65), (n - 1, 1)):
+        note(f"one-pass nchan={nchan} rows {a}..{a + m}")
+        p2, s2 = (host(t) for t in net.infer(Qd[a:a + m].contiguous(), Ud[a:a + m].contiguous()))
+        np.testing.assert_array_equal(p2, ph[a:a + m])
+        np.testing.assert_array_equal(s2, sc[a:a + m])
+
+
 def test_infer_with_unit_weights_matches_oracle():
     """All channel weights 1 (the fused kernel then reads none): against the
     oracle, and equal to the network given the weights explicitly."""
